@@ -1,0 +1,139 @@
+"""CPU oracle for Deep Greedy Switching -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+may import this package.  The GPU library never imports, links or calls
+it, and it shares no code with the GPU library: both sides only take their
+inputs from ``workloads.gen``.
+
+Contents:
+  * ``dgs_ref``  -- pure-Python DGS from the definitions (tiny n).
+  * ``brute``    -- exhaustive optimum (n <= 8).
+  * ``oracle.c`` -- plain C DGS: greedy start, difference evaluation of
+    every agent, DGS with a fresh full re-evaluation after every switch,
+    DGS with exact incremental re-evaluation, and an O(n^3) Hungarian
+    optimum.  Built by ``oracle/build.py`` into ``liboracle.so`` and
+    wrapped below with ctypes.
+
+Every function computes in int64.  Parity unpinned: none -- each function
+is pinned by the tests listed in the repository's design notes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        L.orc_objective.restype = ctypes.c_int64
+        L.orc_objective.argtypes = [i32p, ctypes.c_int32, i32p]
+        L.orc_is_permutation.restype = ctypes.c_int32
+        L.orc_is_permutation.argtypes = [i32p, ctypes.c_int32]
+        L.orc_greedy.restype = None
+        L.orc_greedy.argtypes = [i32p, ctypes.c_int32, i32p]
+        L.orc_scan.restype = None
+        L.orc_scan.argtypes = [i32p, ctypes.c_int32, i32p, i64p, i32p]
+        L.orc_dgs_full.restype = ctypes.c_int64
+        L.orc_dgs_full.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int64), i32p, i32p, i64p,
+                                   ctypes.c_int64]
+        L.orc_dgs_incr.restype = ctypes.c_int64
+        L.orc_dgs_incr.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int64), i32p, i32p, i64p,
+                                   ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        L.orc_hungarian.restype = ctypes.c_int64
+        L.orc_hungarian.argtypes = [i32p, ctypes.c_int32, i32p]
+        _lib = L
+    return _lib
+
+
+NEG_INF = np.iinfo(np.int64).min
+
+
+def _mat(A):
+    A = np.ascontiguousarray(A, dtype=np.int32)
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("benefit matrix must be square")
+    return A
+
+
+def objective(A, tau):
+    A = _mat(A)
+    return int(lib().orc_objective(A, A.shape[0], np.ascontiguousarray(tau, dtype=np.int32)))
+
+
+def is_permutation(tau):
+    tau = np.ascontiguousarray(tau, dtype=np.int32)
+    return bool(lib().orc_is_permutation(tau, tau.shape[0]))
+
+
+def greedy(A):
+    A = _mat(A)
+    tau = np.empty(A.shape[0], dtype=np.int32)
+    lib().orc_greedy(A, A.shape[0], tau)
+    return tau
+
+
+def scan(A, tau):
+    """Per-agent best exchange (gain int64, job int32); NEG_INF/-1 when n == 1."""
+    A = _mat(A)
+    n = A.shape[0]
+    g = np.empty(n, dtype=np.int64)
+    j = np.empty(n, dtype=np.int32)
+    lib().orc_scan(A, n, np.ascontiguousarray(tau, dtype=np.int32), g, j)
+    return g, j
+
+
+def _run(fn, A, init, max_switches, trace_cap, incremental):
+    A = _mat(A)
+    n = A.shape[0]
+    tau = greedy(A) if init is None else np.array(init, dtype=np.int32, copy=True)
+    f = ctypes.c_int64(0)
+    cap = max(int(trace_cap), 0)
+    ti = np.zeros(max(cap, 1), dtype=np.int32)
+    tj = np.zeros(max(cap, 1), dtype=np.int32)
+    tg = np.zeros(max(cap, 1), dtype=np.int64)
+    if incremental:
+        resc = ctypes.c_int64(0)
+        S = fn(A, n, tau, int(max_switches), ctypes.byref(f), ti, tj, tg, cap, ctypes.byref(resc))
+    else:
+        resc = None
+        S = fn(A, n, tau, int(max_switches), ctypes.byref(f), ti, tj, tg, cap)
+    m = min(S, cap)
+    out = dict(tau=tau, f=int(f.value), S=int(S),
+               trace=(ti[:m].copy(), tj[:m].copy(), tg[:m].copy()))
+    if resc is not None:
+        out["rescans"] = int(resc.value)
+    return out
+
+
+def dgs_full(A, init=None, max_switches=-1, trace_cap=0):
+    """DGS with a fresh re-evaluation of every agent after each switch."""
+    return _run(lib().orc_dgs_full, A, init, max_switches, trace_cap, False)
+
+
+def dgs_incr(A, init=None, max_switches=-1, trace_cap=0):
+    """DGS with exact incremental re-evaluation (same result as dgs_full)."""
+    return _run(lib().orc_dgs_incr, A, init, max_switches, trace_cap, True)
+
+
+def hungarian(A):
+    """(optimal benefit, an optimal assignment)."""
+    A = _mat(A)
+    tau = np.empty(A.shape[0], dtype=np.int32)
+    f = lib().orc_hungarian(A, A.shape[0], tau)
+    return int(f), tau

@@ -1,0 +1,99 @@
+"""Pure-Python Deep Greedy Switching, written straight from the definitions.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  Loops over Python
+ints, for tiny instances: it is the first, most literal statement of what
+the method computes, and it pins the C oracle (which must agree with it
+exactly) on many small random instances.
+
+  * objective f(sigma) = sum_i a[i][tau(i)]                   (Section 3)
+  * switch(i, j, sigma): agent i takes job j, the old owner sigma(j) takes
+    tau(i)                                                    (Section 3.3)
+  * the gain of a switch is computed here by building the switched
+    assignment and re-evaluating f from scratch -- not by a gain formula --
+    so this oracle does not depend on any algebra about which terms cancel
+  * ADE (Algorithm 2): scan jobs j' != tau(i) in index order, keep the
+    first strictly better one
+  * switching (Section 3.3, Algorithm 1) under steepest ascent: take the
+    best switch over all agents (lowest agent on ties), apply it if its
+    gain is > 0, re-evaluate every agent, repeat
+  * greedy start (Section 3.1): agents in index order take their best free
+    job, lowest index on ties
+"""
+from __future__ import annotations
+
+NEG_INF = None  # marks "no other job" (n = 1)
+
+
+def objective(A, tau):
+    return sum(A[i][tau[i]] for i in range(len(tau)))
+
+
+def inverse(tau):
+    sigma = [-1] * len(tau)
+    for i, j in enumerate(tau):
+        sigma[j] = i
+    return sigma
+
+
+def switch(i, j, tau):
+    """Return the assignment (as tau) after agent i takes job j."""
+    sigma = inverse(tau)
+    new = list(tau)
+    k = sigma[j]
+    j0 = tau[i]
+    new[i] = j
+    if k >= 0:
+        new[k] = j0
+    return new
+
+
+def greedy(A):
+    n = len(A)
+    taken = [False] * n
+    tau = []
+    for i in range(n):
+        best, bj = None, -1
+        for j in range(n):
+            if taken[j]:
+                continue
+            if best is None or A[i][j] > best:
+                best, bj = A[i][j], j
+        tau.append(bj)
+        taken[bj] = True
+    return tau
+
+
+def ade(A, tau, i):
+    """(gain, job) of agent i's best 2-exchange; (None, -1) if n == 1."""
+    f0 = objective(A, tau)
+    best, bj = NEG_INF, -1
+    for jp in range(len(tau)):
+        if jp == tau[i]:
+            continue
+        g = objective(A, switch(i, jp, tau)) - f0
+        if best is None or g > best:
+            best, bj = g, jp
+    return best, bj
+
+
+def scan(A, tau):
+    return [ade(A, tau, i) for i in range(len(tau))]
+
+
+def dgs(A, init=None, max_switches=-1):
+    """Returns (tau, f, S, trace) with trace = [(agent, job, gain), ...]."""
+    tau = list(greedy(A) if init is None else init)
+    S = 0
+    trace = []
+    while max_switches < 0 or S < max_switches:
+        rb = scan(A, tau)
+        bi, bg = -1, 0
+        for i, (g, _) in enumerate(rb):
+            if g is not None and g > bg:
+                bi, bg = i, g
+        if bi < 0:
+            break
+        trace.append((bi, rb[bi][1], bg))
+        tau = switch(bi, rb[bi][1], tau)
+        S += 1
+    return tau, objective(A, tau), S, trace

@@ -1,0 +1,238 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each check names what fixes the expected value: a hand-worked example of
+the paper's definitions (tests/golden/worked_examples.txt), a closed form,
+brute-force enumeration, an independent library routine, or an
+implementation written from a different statement of the same definition
+(the pure-Python oracle evaluates every exchange by rebuilding the
+assignment and re-summing the objective, with no gain algebra).
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+import oracle
+from oracle import brute, dgs_ref
+from tests.golden_io import ints, matrix, worked_examples
+from workloads import gen
+
+EX = worked_examples()
+
+
+def _f(A, tau):
+    return int(sum(int(A[i, tau[i]]) for i in range(len(tau))))
+
+
+def _swap_gains_by_resumming(A, tau):
+    """All 2-exchange gains, each by building the exchanged assignment."""
+    n = len(tau)
+    f0 = _f(A, tau)
+    out = {}
+    for i, k in itertools.combinations(range(n), 2):
+        t = list(tau)
+        t[i], t[k] = t[k], t[i]
+        out[(i, k)] = _f(A, t) - f0
+    return out
+
+
+# ---- worked examples ----------------------------------------------------------------
+
+
+@pytest.mark.parametrize("name", sorted(EX))
+def test_worked_example_c_oracle(name):
+    ex = EX[name]
+    A = matrix(ex["A"])
+    assert list(oracle.greedy(A)) == ints(ex["greedy"])
+    assert oracle.objective(A, oracle.greedy(A)) == int(ex["greedy_f"])
+    if "scan0_gain" in ex:
+        g, j = oracle.scan(A, oracle.greedy(A))
+        assert list(g) == ints(ex["scan0_gain"])
+        assert list(j) == ints(ex["scan0_job"])
+    for run in (oracle.dgs_full, oracle.dgs_incr):
+        r = run(A)
+        assert list(r["tau"]) == ints(ex["tau"]), name
+        assert r["f"] == int(ex["f"])
+        assert r["S"] == int(ex["S"])
+    if "final_gain" in ex:
+        g, j = oracle.scan(A, np.array(ints(ex["tau"]), dtype=np.int32))
+        assert list(g) == ints(ex["final_gain"])
+        assert list(j) == ints(ex["final_job"])
+    assert oracle.hungarian(A)[0] == int(ex["opt"])
+    assert brute.optimum(A.tolist())[0] == int(ex["opt"])
+
+
+@pytest.mark.parametrize("name", sorted(EX))
+def test_worked_example_python_oracle(name):
+    ex = EX[name]
+    A = matrix(ex["A"]).tolist()
+    assert dgs_ref.greedy(A) == ints(ex["greedy"])
+    if "scan0_gain" in ex:
+        rb = dgs_ref.scan(A, dgs_ref.greedy(A))
+        assert [g for g, _ in rb] == ints(ex["scan0_gain"])
+        assert [j for _, j in rb] == ints(ex["scan0_job"])
+    tau, f, S, _ = dgs_ref.dgs(A)
+    assert tau == ints(ex["tau"]) and f == int(ex["f"]) and S == int(ex["S"])
+
+
+def test_single_agent_scan_sentinel():
+    g, j = oracle.scan(np.array([[3]], dtype=np.int32), np.array([0], dtype=np.int32))
+    assert g[0] == oracle.NEG_INF and j[0] == -1
+
+
+# ---- closed forms ------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 300])
+def test_constant_matrix(n):
+    # every permutation has the same benefit: identity by the tie rule, no switch
+    A = np.full((n, n), 17, dtype=np.int32)
+    r = oracle.dgs_full(A)
+    assert list(r["tau"]) == list(range(n)) and r["S"] == 0 and r["f"] == 17 * n
+
+
+@pytest.mark.parametrize("n,seed", [(3, 1), (50, 2), (257, 3)])
+def test_separable_matrix(n, seed):
+    # a_ij = r_i + c_j: all permutations tie, so every gain is 0 and no switch
+    # happens; greedy takes columns in order of (c desc, j asc).
+    r = gen.uniform_matrix(n, 0, 1000, seed)[:, 0]
+    c = gen.uniform_matrix(n, 0, 50, seed + 100)[0]  # many equal c_j
+    A = (r[:, None] + c[None, :]).astype(np.int32)
+    expect = sorted(range(n), key=lambda j: (-int(c[j]), j))
+    out = oracle.dgs_incr(A)
+    assert list(out["tau"]) == expect and out["S"] == 0
+    g, _ = oracle.scan(A, out["tau"])
+    if n > 1:
+        assert (g == 0).all()
+
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (7, 2), (100, 3), (1000, 4)])
+def test_rank_one_matrix_reaches_rank_matching(n, seed):
+    # a_ij = u_i * c_j, distinct positive u, c: exchange (i, k) gains
+    # (u_i - u_k)(c_tau(k) - c_tau(i)), so the only 2-swap local optimum is the
+    # matching of u and c by rank, which is also the optimum (rearrangement).
+    rng_u = gen.permutation(4 * n, seed)[:n].astype(np.int64) + 1
+    rng_c = gen.permutation(4 * n, seed + 7)[:n].astype(np.int64) + 1
+    A = (rng_u[:, None] * rng_c[None, :]).astype(np.int32)
+    out = oracle.dgs_incr(A)
+    order_u = np.argsort(rng_u)
+    order_c = np.argsort(rng_c)
+    expect = np.empty(n, dtype=np.int64)
+    expect[order_u] = order_c
+    assert list(out["tau"]) == list(expect)
+    assert out["f"] == int(np.sum(np.sort(rng_u) * np.sort(rng_c)))
+    if n <= 100:
+        assert oracle.dgs_full(A)["f"] == out["f"]
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (9, 2), (500, 3)])
+def test_scaled_permutation_matrix(n, seed):
+    pi = gen.permutation(n, seed)
+    A = np.zeros((n, n), dtype=np.int32)
+    A[np.arange(n), pi] = 1000
+    out = oracle.dgs_full(A) if n < 100 else oracle.dgs_incr(A)
+    assert list(out["tau"]) == list(pi) and out["S"] == 0 and out["f"] == 1000 * n
+
+
+# ---- brute force and exact optimum -----------------------------------------------------
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_small_instances_against_brute_force(seed):
+    n = 1 + seed % 8
+    vmax = 3 if seed % 3 == 0 else 50  # heavy ties for every third seed
+    A = gen.uniform_matrix(n, -vmax if seed % 5 == 0 else 0, vmax, 1000 + seed)
+    opt, _ = brute.optimum(A.tolist())
+    r = oracle.dgs_full(A, trace_cap=64)
+    assert oracle.is_permutation(r["tau"])
+    assert r["f"] == _f(A, r["tau"]) <= opt
+    if n <= 2:
+        assert r["f"] == opt
+    # 2-swap local optimality at exit, every gain by re-summing
+    assert max(_swap_gains_by_resumming(A, r["tau"]).values(), default=0) <= 0
+    # every applied switch has gain > 0 and the recorded gain is the true
+    # change of the objective
+    tau = list(oracle.greedy(A))
+    f = _f(A, tau)
+    for i, j, g in zip(*r["trace"]):
+        assert g > 0
+        t2 = dgs_ref.switch(int(i), int(j), tau)
+        assert _f(A, t2) - f == g
+        tau, f = t2, _f(A, t2)
+    assert tau == list(r["tau"])
+    assert oracle.hungarian(A)[0] == opt
+
+
+@pytest.mark.parametrize("n,seed", [(16, 1), (64, 2), (200, 3), (513, 4)])
+def test_hungarian_matches_scipy(n, seed):
+    A = gen.uniform_matrix(n, -500, 1000, seed)
+    f, tau = oracle.hungarian(A)
+    rows, cols = scipy.optimize.linear_sum_assignment(A.astype(np.int64), maximize=True)
+    assert f == int(A[rows, cols].astype(np.int64).sum())
+    assert oracle.is_permutation(tau) and _f(A, tau) == f
+
+
+# ---- two statements of the same definition agree ----------------------------------------
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_python_and_c_oracles_agree(seed):
+    n = [3, 4, 5, 6, 8, 11, 13, 16][seed % 8]
+    lo, hi = [(0, 3), (0, 10), (-5, 5), (0, 1000)][seed % 4]
+    A = gen.uniform_matrix(n, lo, hi, 5000 + seed)
+    tau_p, f_p, S_p, tr_p = dgs_ref.dgs(A.tolist())
+    for run in (oracle.dgs_full, oracle.dgs_incr):
+        r = run(A, trace_cap=10_000)
+        assert list(r["tau"]) == tau_p and r["f"] == f_p and r["S"] == S_p
+        assert [tuple(int(x) for x in t) for t in zip(*r["trace"])] == tr_p
+    g, j = oracle.scan(A, oracle.greedy(A))
+    rb = dgs_ref.scan(A.tolist(), dgs_ref.greedy(A.tolist()))
+    assert list(g) == [x for x, _ in rb] and list(j) == [y for _, y in rb]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_full_and_incremental_agree(seed):
+    n = [40, 97, 128, 255, 256, 300][seed % 6]
+    if seed % 3 == 0:
+        A = gen.uniform_matrix(n, 0, 4, 7000 + seed)  # many exact ties
+    elif seed % 3 == 1:
+        A = gen.lowrank_matrix(n, 7000 + seed)
+    else:
+        A = gen.uniform_matrix(n, -1000, 1000, 7000 + seed)
+    a = oracle.dgs_full(A, trace_cap=100_000)
+    b = oracle.dgs_incr(A, trace_cap=100_000)
+    assert (a["tau"] == b["tau"]).all() and a["f"] == b["f"] and a["S"] == b["S"]
+    for x, y in zip(a["trace"], b["trace"]):
+        assert (x == y).all()
+
+
+def test_random_start_and_resume():
+    # the paper's random start (Section 3.1) and resuming from a prefix state:
+    # steepest ascent depends only on the current assignment.
+    A = gen.lowrank_matrix(300, 3)
+    start = gen.permutation(300, 11)
+    full = oracle.dgs_incr(A, init=start, trace_cap=100_000)
+    assert full["S"] > 10
+    for k in (0, 1, 5, full["S"] // 2, full["S"]):
+        part = oracle.dgs_full(A, init=start, max_switches=k)
+        assert part["S"] == k
+        # the prefix state equals replaying the first k switches
+        tau = list(start)
+        for i, j in zip(full["trace"][0][:k], full["trace"][1][:k]):
+            tau = dgs_ref.switch(int(i), int(j), tau)
+        assert list(part["tau"]) == tau
+        rest = oracle.dgs_incr(A, init=part["tau"])
+        assert (rest["tau"] == full["tau"]).all() and rest["f"] == full["f"]
+        assert rest["S"] == full["S"] - k
+
+
+def test_objective_accounting():
+    A = gen.uniform_matrix(256, 0, 1000, 1)
+    r = oracle.dgs_full(A, trace_cap=10_000)
+    f0 = oracle.objective(A, oracle.greedy(A))
+    assert r["f"] == f0 + int(r["trace"][2].sum())
+    assert (r["trace"][2] > 0).all()
+    assert r["f"] <= oracle.hungarian(A)[0]
