@@ -1,0 +1,179 @@
+/*
+ * dgs.h -- Deep Greedy Switching (DGS) for the Linear Sum Assignment
+ * Problem on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: Roverso, Naiem, El-Beltagy, El-Ansary, "GPU-Based Heuristic
+ * Solver for Linear Sum Assignment Problems Under Real-time Constraints"
+ * (arXiv:1106.5694).
+ *
+ * Problem (Section 3): n agents, n jobs, integer benefit a_ij of giving job
+ * j to agent i; find a permutation tau (tau[i] = job of agent i) with a
+ * large total benefit f = sum_i a[i][tau[i]].  The benefit matrix is
+ * row-major int32: benefit[i * n + j] = a_ij.
+ *
+ * What every solve computes (Sections 3.1-3.3, Algorithms 1 and 2):
+ *   1. greedy start: agents 0..n-1 in order, each takes its best free job
+ *      (lowest job index on ties);
+ *   2. repeat: every agent finds its best 2-exchange (ADE: agent i takes job
+ *      j, the owner of j takes i's old job; gain = change of f, lowest j on
+ *      ties), the best exchange over all agents is applied (largest gain,
+ *      lowest agent on ties) if its gain is > 0, and the agents are
+ *      re-evaluated; stop when no exchange improves f.
+ *   The result (tau, f, number of switches) is a deterministic function of
+ *   the input; it is bit-identical to a plain CPU implementation of the
+ *   same steps.
+ *
+ * Value range: every |a_ij| must be <= DGS_MAX_ABS_BENEFIT (2^29 - 1), so
+ * that every exchange gain (a sum of four entries) fits in int32.  Larger
+ * values are rejected with DGS_E_RANGE.
+ *
+ * Errors: every entry point returns a dgs_status.  On any error the output
+ * buffers are left untouched and dgs_last_error() describes the failure
+ * (thread-local).  No entry point aborts the process.
+ *
+ * Memory: the caller owns every buffer it passes.  Inputs are only read for
+ * the duration of the call (server: until the request completes).  The
+ * library owns its device memory and streams.
+ */
+#ifndef DGS_H
+#define DGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dgs_status {
+    DGS_OK = 0,
+    DGS_E_INVAL = 1,  /* NULL pointer, n < 1, n > max, bad permutation, bad ticket */
+    DGS_E_RANGE = 2,  /* some |a_ij| > DGS_MAX_ABS_BENEFIT */
+    DGS_E_NOMEM = 3,  /* device allocation failed or request exceeds the budget */
+    DGS_E_DEVICE = 4, /* HIP runtime error or no usable GPU */
+    DGS_E_AGAIN = 5   /* server: request not finished yet */
+} dgs_status;
+
+#define DGS_MAX_ABS_BENEFIT 536870911 /* 2^29 - 1 */
+#define DGS_MAX_N 1048576
+
+/* dgs_options.flags */
+#define DGS_DEVICE_PTRS 0x1u /* benefit, assign_out, init_assign are device pointers */
+
+typedef struct dgs_options {
+    /* Stop after this many switches (< 0: run to the end).  The paper's
+     * anytime property (Section 3): DGS always holds a full assignment, so
+     * stopping early returns the assignment reached so far. */
+    int64_t max_switches;
+    /* NULL: greedy start.  Else a permutation of 0..n-1 used as the start
+     * (the paper's random start, Section 3.1, or a resumed state).  A
+     * non-permutation is rejected with DGS_E_INVAL. */
+    const int32_t *init_assign;
+    uint32_t flags;
+    /* hipStream_t to run on (NULL: the library's own stream).  The call is
+     * synchronous either way: it returns when the result is written. */
+    void *stream;
+} dgs_options;
+
+typedef struct dgs_result {
+    int64_t initial_benefit; /* f of the start assignment */
+    int64_t total_benefit;   /* f of the returned assignment */
+    int64_t switches;        /* number of 2-exchanges applied */
+    float device_ms;         /* device time of the solve (HIP events) */
+} dgs_result;
+
+/* Solve one instance with default options (greedy start, run to the end).
+ * benefit: host pointer, n*n int32, row-major.  assign_out: host pointer,
+ * n int32; on success assign_out[i] = job of agent i. */
+dgs_status dgs_solve(const int32_t *benefit, int32_t n, int32_t *assign_out);
+
+/* As dgs_solve with options (may be NULL) and an optional result record
+ * (res may be NULL). */
+dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out,
+                        const dgs_options *opt, dgs_result *res);
+
+/* Solve `count` independent instances of possibly different sizes in one
+ * device pass (one persistent launch; small instances run one per
+ * workgroup).  benefits[b] / assign_outs[b] / ns[b] describe instance b
+ * (host pointers, or device pointers with DGS_DEVICE_PTRS).  results may be
+ * NULL, else it has `count` entries.  opt may be NULL; its max_switches
+ * applies to every instance; init_assign must be NULL.  Every instance's
+ * result is identical to dgs_solve_ex on that instance alone. */
+dgs_status dgs_solve_batched(int32_t count, const int32_t *const *benefits, const int32_t *ns,
+                             int32_t *const *assign_outs, dgs_result *results,
+                             const dgs_options *opt);
+
+/* Difference evaluation (Section 3.2, Algorithm 2) of every agent for a
+ * given assignment: for each agent i, the best 2-exchange gain over all
+ * jobs j != assign[i] and the job reaching it (lowest j on ties).  The
+ * best is reported even when it is <= 0.  For n == 1 agent 0 has no
+ * exchange: gain_out[0] = INT64_MIN, job_out[0] = -1.
+ * assign: n int32 permutation.  gain_out: n int64.  job_out: n int32.
+ * Pointers are host pointers unless opt->flags has DGS_DEVICE_PTRS (then
+ * benefit, assign, gain_out and job_out are all device pointers).  opt may
+ * be NULL; only flags and stream are used.  res may be NULL; its device_ms
+ * is the time of the evaluation kernels. */
+dgs_status dgs_diff_eval(const int32_t *benefit, int32_t n, const int32_t *assign,
+                         int64_t *gain_out, int32_t *job_out, const dgs_options *opt,
+                         dgs_result *res);
+
+/* ---- Serving: continuous batching of periodic LSAP requests ---------- */
+
+typedef struct dgs_server dgs_server;
+
+typedef struct dgs_server_config {
+    uint64_t hbm_budget_bytes; /* device bytes the server may hold for requests (0: 64 GiB) */
+    int32_t max_slots;         /* requests resident on the device at once (0: 64) */
+    int32_t max_n;             /* largest accepted n (0: 16384) */
+} dgs_server_config;
+
+typedef struct dgs_server_stats {
+    int64_t submitted;
+    int64_t completed;
+    int64_t queued;      /* admitted to the queue, not yet on the device */
+    int64_t resident;    /* on the device now */
+    double inst_per_s;   /* completed / (last completion - first submit) */
+    double p50_us;       /* submit -> result ready, over completed requests */
+    double p99_us;
+} dgs_server_stats;
+
+/* Footprint of one request of size n on the device, in bytes. */
+uint64_t dgs_server_footprint(int32_t n);
+
+dgs_status dgs_server_create(const dgs_server_config *cfg, dgs_server **out);
+
+/* Queue one request.  benefit: host pointer, n*n int32, row-major; it must
+ * stay valid until the ticket completes.  Never waits for the GPU.
+ * DGS_E_NOMEM if the request can never fit the budget; DGS_E_INVAL for
+ * n < 1 or n > max_n. */
+dgs_status dgs_server_submit(dgs_server *s, const int32_t *benefit, int32_t n,
+                             uint64_t *ticket_out);
+
+/* DGS_E_AGAIN while pending; DGS_OK once done (assign_out, n int32, is
+ * written and the ticket is consumed).  res may be NULL. */
+dgs_status dgs_server_poll(dgs_server *s, uint64_t ticket, int32_t *assign_out,
+                           dgs_result *res);
+
+/* As poll, waiting up to timeout_us (< 0: forever). */
+dgs_status dgs_server_wait(dgs_server *s, uint64_t ticket, int32_t *assign_out,
+                           dgs_result *res, int64_t timeout_us);
+
+dgs_status dgs_server_stats_get(dgs_server *s, dgs_server_stats *out);
+
+/* Waits for every queued request, then frees everything. */
+void dgs_server_destroy(dgs_server *s);
+
+/* ---- Misc --------------------------------------------------------------- */
+
+const char *dgs_status_string(dgs_status st);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char *dgs_last_error(void);
+
+/* Library version string. */
+const char *dgs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGS_H */

@@ -1,0 +1,458 @@
+// C ABI of the DGS library (declared in include/dgs.h).
+//
+// Host side only: argument checks, device workspaces, stream handling and
+// the order of kernel launches.  Every step of the method itself runs in
+// the kernels of dgs_kernels.hip; there is no CPU fallback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dgs.h"
+#include "dgs_internal.h"
+
+namespace dgs {
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+#define DGS_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return DGS_E_DEVICE;                                                            \
+        }                                                                                   \
+    } while (0)
+
+// ---- device context ---------------------------------------------------------------
+
+struct Context {
+    std::once_flag once;
+    int device = -1;
+    int loop_grid = 0;
+    hipStream_t stream = nullptr;
+    dgs_status init_status = DGS_OK;
+    std::string init_error;
+    // Cooperative switch loops need every workgroup resident; one at a time.
+    std::mutex loop_mu;
+};
+
+Context g_ctx;
+
+dgs_status ensure_context() {
+    std::call_once(g_ctx.once, [] {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || count < 1) {
+            g_ctx.init_status = DGS_E_DEVICE;
+            g_ctx.init_error = std::string("no HIP device: ") + hipGetErrorString(e);
+            return;
+        }
+        if (hipGetDevice(&g_ctx.device) != hipSuccess) g_ctx.device = 0;
+        g_ctx.loop_grid = loop_grid_size(g_ctx.device);
+        if (g_ctx.loop_grid < 1) {
+            g_ctx.init_status = DGS_E_DEVICE;
+            g_ctx.init_error = "cannot size the cooperative switch-loop grid";
+            return;
+        }
+        if (hipStreamCreateWithFlags(&g_ctx.stream, hipStreamNonBlocking) != hipSuccess) {
+            g_ctx.init_status = DGS_E_DEVICE;
+            g_ctx.init_error = "hipStreamCreate failed";
+        }
+    });
+    if (g_ctx.init_status != DGS_OK) set_error("%s", g_ctx.init_error.c_str());
+    return g_ctx.init_status;
+}
+
+// ---- workspaces -----------------------------------------------------------------------
+// One workspace holds the device buffers of one instance of size <= cap.
+// Workspaces are cached (released ones are reused by later calls of a
+// size they fit) so repeated solves do not pay for allocation.
+
+struct Workspace {
+    int32_t cap = 0;
+    bool has_acopy = false;
+    int32_t *acopy = nullptr;  // device copy of a host benefit matrix
+    int32_t *at = nullptr;
+    int32_t *w = nullptr;
+    char *vec = nullptr;  // vectors + scratch
+    size_t vec_bytes = 0;
+    int64_t *host_stats = nullptr;  // pinned: stats[8] then flags[4] (as int64)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+std::mutex g_ws_mu;
+std::multimap<int32_t, Workspace *> g_ws_free;
+
+// Byte layout of the vector block of a workspace.  Every piece starts on a
+// 256-byte boundary; vec_layout() is the single source of the offsets used
+// both to size the allocation and to carve it.
+struct VecLayout {
+    size_t tau, sigma, d, bc, bk, bb, recs, barrier, stats, flags, total;
+};
+
+VecLayout vec_layout(int32_t n, int grid) {
+    VecLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    L.tau = take((size_t)n * 4);
+    L.sigma = take((size_t)n * 4);
+    L.d = take((size_t)n * 4);
+    L.bc = take((size_t)n * 4);
+    L.bk = take((size_t)n * 8);
+    L.bb = take((size_t)n * 8);
+    L.recs = take(2 * (size_t)grid * loop_record_bytes());
+    L.barrier = take(256);
+    L.stats = take(8 * sizeof(int64_t));
+    L.flags = take(4 * sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
+void free_ws(Workspace *w) {
+    if (!w) return;
+    if (w->acopy) (void)hipFree(w->acopy);
+    if (w->at) (void)hipFree(w->at);
+    if (w->w) (void)hipFree(w->w);
+    if (w->vec) (void)hipFree(w->vec);
+    if (w->host_stats) (void)hipHostFree(w->host_stats);
+    if (w->ev0) (void)hipEventDestroy(w->ev0);
+    if (w->ev1) (void)hipEventDestroy(w->ev1);
+    delete w;
+}
+
+dgs_status alloc_ws(int32_t n, bool need_acopy, Workspace **out) {
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        for (auto it = g_ws_free.lower_bound(n); it != g_ws_free.end(); ++it) {
+            // do not hand a huge workspace to a tiny problem
+            if (it->first > 2 * n + 1024) break;
+            if (need_acopy && !it->second->has_acopy) continue;
+            *out = it->second;
+            g_ws_free.erase(it);
+            return DGS_OK;
+        }
+    }
+    Workspace *w = new Workspace();
+    w->cap = n;
+    const size_t mat = (size_t)n * (size_t)n * sizeof(int32_t);
+    auto fail = [&](const char *what) {
+        set_error("device allocation of %s for n=%d failed", what, n);
+        free_ws(w);
+        return DGS_E_NOMEM;
+    };
+    if (need_acopy) {
+        if (hipMalloc((void **)&w->acopy, mat) != hipSuccess) return fail("benefit copy");
+        w->has_acopy = true;
+    }
+    if (hipMalloc((void **)&w->at, mat) != hipSuccess) return fail("transpose");
+    if (hipMalloc((void **)&w->w, mat) != hipSuccess) return fail("working matrix");
+    w->vec_bytes = vec_layout(n, g_ctx.loop_grid).total;
+    if (hipMalloc((void **)&w->vec, w->vec_bytes) != hipSuccess) return fail("vectors");
+    if (hipHostMalloc((void **)&w->host_stats, 16 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+        return fail("pinned stats");
+    if (hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess) {
+        set_error("hipEventCreate failed");
+        free_ws(w);
+        return DGS_E_DEVICE;
+    }
+    *out = w;
+    return DGS_OK;
+}
+
+void release_ws(Workspace *w) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    g_ws_free.emplace(w->cap, w);
+}
+
+// Carve an Instance out of a workspace (n <= w->cap, grid <= loop grid).
+Instance carve(Workspace *w, const int32_t *A, int32_t n, int grid) {
+    Instance I;
+    I.n = n;
+    I.A = A;
+    I.AT = w->at;
+    I.W = w->w;
+    const VecLayout L = vec_layout(n, grid);
+    char *p = w->vec;
+    I.tau = (int32_t *)(p + L.tau);
+    I.sigma = (int32_t *)(p + L.sigma);
+    I.d = (int32_t *)(p + L.d);
+    I.bc = (int32_t *)(p + L.bc);
+    I.bk = (u64 *)(p + L.bk);
+    I.bb = (u64 *)(p + L.bb);
+    I.recs = p + L.recs;
+    I.barrier = (uint32_t *)(p + L.barrier);
+    I.stats = (int64_t *)(p + L.stats);
+    I.flags = (int32_t *)(p + L.flags);
+    return I;
+}
+
+bool is_perm_host(const int32_t *p, int32_t n) {
+    std::vector<char> seen((size_t)n, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        if (p[i] < 0 || p[i] >= n || seen[(size_t)p[i]]) return false;
+        seen[(size_t)p[i]] = 1;
+    }
+    return true;
+}
+
+// Reads an init assignment (host or device) and checks it on the host.
+dgs_status check_init(const int32_t *init, int32_t n, bool dev, hipStream_t s) {
+    std::vector<int32_t> h;
+    const int32_t *p = init;
+    if (dev) {
+        h.resize((size_t)n);
+        DGS_HIP(hipMemcpyAsync(h.data(), init, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        DGS_HIP(hipStreamSynchronize(s));
+        p = h.data();
+    }
+    if (!is_perm_host(p, n)) {
+        set_error("init_assign is not a permutation of 0..n-1");
+        return DGS_E_INVAL;
+    }
+    return DGS_OK;
+}
+
+enum class Mode { Solve, DiffEval };
+
+struct Call {
+    const int32_t *benefit;
+    int32_t n;
+    const int32_t *assign_in;  // start (solve) or the assignment to evaluate
+    int64_t max_switches;
+    bool dev;
+    hipStream_t stream;
+};
+
+// The whole device pipeline of one instance.
+dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *gain_out, int32_t *job_out,
+                        dgs_result *res) {
+    const int32_t n = c.n;
+    hipStream_t s = c.stream;
+    if (c.assign_in) {
+        dgs_status st = check_init(c.assign_in, n, c.dev, s);
+        if (st != DGS_OK) return st;
+    }
+    Workspace *w = nullptr;
+    dgs_status st = alloc_ws(n, !c.dev, &w);
+    if (st != DGS_OK) return st;
+    struct Guard {
+        Workspace *w;
+        ~Guard() { release_ws(w); }
+    } guard{w};
+
+    const int grid = std::max(1, std::min(g_ctx.loop_grid, (int)n));
+    if (vec_layout(n, grid).total > w->vec_bytes) {
+        set_error("internal: workspace too small for n=%d", n);
+        return DGS_E_NOMEM;
+    }
+    const int32_t *A = c.dev ? c.benefit : w->acopy;
+    Instance I = carve(w, A, n, grid);
+    const size_t mat = (size_t)n * (size_t)n * sizeof(int32_t);
+    if (!c.dev) DGS_HIP(hipMemcpyAsync(w->acopy, c.benefit, mat, hipMemcpyHostToDevice, s));
+
+    DGS_HIP(hipEventRecord(w->ev0, s));
+    DGS_HIP(hipMemsetAsync(I.barrier, 0, 256, s));
+    DGS_HIP(hipMemsetAsync(I.stats, 0, 8 * sizeof(int64_t), s));
+    DGS_HIP(hipMemsetAsync(I.flags, 0, 4 * sizeof(int32_t), s));
+    DGS_HIP(launch_range_check(A, (int64_t)n * n, I.flags, s));
+    if (c.assign_in) {
+        DGS_HIP(hipMemcpyAsync(I.tau, c.assign_in, (size_t)n * 4,
+                               c.dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        DGS_HIP(launch_invert_checked(I.tau, n, I.sigma, I.flags + 1, s));
+    } else {
+        DGS_HIP(launch_greedy(A, n, I.tau, I.sigma, s));
+    }
+    DGS_HIP(launch_transpose(A, I.AT, n, s));
+    DGS_HIP(launch_build_w(A, I.tau, n, I.W, I.d, I.stats + 2, s));
+    DGS_HIP(launch_scan_rows(I, s));
+    if (mode == Mode::Solve) {
+        // The loop exits at once when the range check failed.
+        std::lock_guard<std::mutex> lk(g_ctx.loop_mu);
+        DGS_HIP(launch_switch_loop(I, c.max_switches, grid, s));
+    } else {
+        DGS_HIP(launch_export_best(I, gain_out, job_out, s));
+    }
+    DGS_HIP(hipEventRecord(w->ev1, s));
+    DGS_HIP(hipMemcpyAsync(w->host_stats, I.stats, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DGS_HIP(hipMemcpyAsync(w->host_stats + 8, I.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DGS_HIP(hipStreamSynchronize(s));
+    const int32_t *flags = (const int32_t *)(w->host_stats + 8);
+    if (flags[0]) {
+        set_error("benefit entry outside [-(2^29-1), 2^29-1]");
+        return DGS_E_RANGE;
+    }
+    if (flags[1]) {
+        set_error("init_assign is not a permutation of 0..n-1");
+        return DGS_E_INVAL;
+    }
+    if (mode == Mode::Solve) {
+        DGS_HIP(hipMemcpyAsync(assign_out, I.tau, (size_t)n * 4,
+                               c.dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+        DGS_HIP(hipStreamSynchronize(s));
+    }
+    if (res) {
+        float ms = 0.f;
+        DGS_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+        const int64_t *hs = w->host_stats;
+        res->initial_benefit = hs[2];
+        res->total_benefit = hs[2] + hs[1];
+        res->switches = hs[0];
+        res->device_ms = ms;
+    }
+    return DGS_OK;
+}
+
+dgs_status check_common(const int32_t *benefit, int32_t n, const void *out) {
+    if (!benefit || !out) {
+        set_error("NULL pointer argument");
+        return DGS_E_INVAL;
+    }
+    if (n < 1 || n > DGS_MAX_N) {
+        set_error("n=%d outside [1, %d]", n, DGS_MAX_N);
+        return DGS_E_INVAL;
+    }
+    return DGS_OK;
+}
+
+}  // namespace
+}  // namespace dgs
+
+using namespace dgs;
+
+extern "C" {
+
+const char *dgs_status_string(dgs_status st) {
+    switch (st) {
+        case DGS_OK: return "ok";
+        case DGS_E_INVAL: return "invalid argument";
+        case DGS_E_RANGE: return "benefit out of range";
+        case DGS_E_NOMEM: return "out of device memory or budget";
+        case DGS_E_DEVICE: return "device error";
+        case DGS_E_AGAIN: return "not finished";
+    }
+    return "unknown status";
+}
+
+const char *dgs_last_error(void) { return g_last_error.c_str(); }
+
+const char *dgs_version(void) { return "dgs-gfx950 0.1"; }
+
+dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out, const dgs_options *opt,
+                        dgs_result *res) {
+    g_last_error.clear();
+    dgs_status st = check_common(benefit, n, assign_out);
+    if (st != DGS_OK) return st;
+    if ((st = ensure_context()) != DGS_OK) return st;
+    Call c;
+    c.benefit = benefit;
+    c.n = n;
+    c.assign_in = opt ? opt->init_assign : nullptr;
+    c.max_switches = opt ? opt->max_switches : -1;
+    c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
+    c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
+    return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
+}
+
+dgs_status dgs_solve(const int32_t *benefit, int32_t n, int32_t *assign_out) {
+    return dgs_solve_ex(benefit, n, assign_out, nullptr, nullptr);
+}
+
+dgs_status dgs_diff_eval(const int32_t *benefit, int32_t n, const int32_t *assign, int64_t *gain_out,
+                         int32_t *job_out, const dgs_options *opt, dgs_result *res) {
+    g_last_error.clear();
+    dgs_status st = check_common(benefit, n, gain_out);
+    if (st != DGS_OK) return st;
+    if (!assign || !job_out) {
+        set_error("NULL pointer argument");
+        return DGS_E_INVAL;
+    }
+    if ((st = ensure_context()) != DGS_OK) return st;
+    Call c;
+    c.benefit = benefit;
+    c.n = n;
+    c.assign_in = assign;
+    c.max_switches = 0;
+    c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
+    c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
+    if (c.dev) return run_instance(c, Mode::DiffEval, nullptr, gain_out, job_out, res);
+    // host outputs: evaluate into device buffers, then copy
+    int64_t *dg = nullptr;
+    int32_t *dj = nullptr;
+    if (hipMalloc((void **)&dg, (size_t)n * 8) != hipSuccess || hipMalloc((void **)&dj, (size_t)n * 4) != hipSuccess) {
+        if (dg) (void)hipFree(dg);
+        set_error("device allocation failed");
+        return DGS_E_NOMEM;
+    }
+    st = run_instance(c, Mode::DiffEval, nullptr, dg, dj, res);
+    if (st == DGS_OK) {
+        if (hipMemcpy(gain_out, dg, (size_t)n * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(job_out, dj, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+            set_error("copy of evaluation results failed");
+            st = DGS_E_DEVICE;
+        }
+    }
+    (void)hipFree(dg);
+    (void)hipFree(dj);
+    return st;
+}
+
+dgs_status dgs_solve_batched(int32_t count, const int32_t *const *benefits, const int32_t *ns,
+                             int32_t *const *assign_outs, dgs_result *results, const dgs_options *opt) {
+    g_last_error.clear();
+    if (count < 0 || (count > 0 && (!benefits || !ns || !assign_outs))) {
+        set_error("bad batch arguments");
+        return DGS_E_INVAL;
+    }
+    if (opt && opt->init_assign) {
+        set_error("init_assign is not supported for batches");
+        return DGS_E_INVAL;
+    }
+    for (int32_t b = 0; b < count; ++b) {
+        dgs_status st = check_common(benefits[b], ns[b], assign_outs[b]);
+        if (st != DGS_OK) return st;
+    }
+    dgs_status st = ensure_context();
+    if (st != DGS_OK) return st;
+    for (int32_t b = 0; b < count; ++b) {
+        Call c;
+        c.benefit = benefits[b];
+        c.n = ns[b];
+        c.assign_in = nullptr;
+        c.max_switches = opt ? opt->max_switches : -1;
+        c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
+        c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
+        st = run_instance(c, Mode::Solve, assign_outs[b], nullptr, nullptr, results ? &results[b] : nullptr);
+        if (st != DGS_OK) return st;
+    }
+    return DGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Internal interface between the C ABI (dgs_api.cpp) and the gfx950
+// kernels (dgs_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgs {
+
+typedef unsigned long long u64;
+
+// Device state of one single-instance solve.  Layout (all row-major int32,
+// n x n, 64-bit element offsets):
+//   A   the caller's benefit matrix a_ij (read-only)
+//   AT  its transpose: AT[j][i] = a_ij (read-only after the build)
+//   W   the assignment-ordered matrix W[r][c] = a[r][tau(c)]: the benefit
+//       agent r would get from agent c's current job.  Kept current across
+//       switches (two entries per row change per switch).
+// Vectors (n entries): tau (job of agent), sigma (agent of job), d (current
+// benefit of agent c, d[c] = W[c][c]).
+// Per-agent best record: bk = packed key of the best exchange (gain, job),
+// bb = bound key (every other exchange of the agent is <= bb), bc = the
+// partner agent of the best exchange.
+struct Instance {
+    int32_t n = 0;
+    const int32_t *A = nullptr;
+    int32_t *AT = nullptr;
+    int32_t *W = nullptr;
+    int32_t *tau = nullptr;
+    int32_t *sigma = nullptr;
+    int32_t *d = nullptr;
+    u64 *bk = nullptr;
+    u64 *bb = nullptr;
+    int32_t *bc = nullptr;
+    // scratch for the switch loop and small reductions
+    void *recs = nullptr;        // 2 x grid records
+    uint32_t *barrier = nullptr; // grid barrier counter
+    int64_t *stats = nullptr;    // [0] switches, [1] gain sum, [2] f0, [3] rescans
+    int32_t *flags = nullptr;    // [0] range error, [1] permutation error
+};
+
+size_t loop_record_bytes();
+int loop_grid_size(int device);
+
+hipError_t launch_range_check(const int32_t *A, int64_t count, int32_t *flag, hipStream_t s);
+hipError_t launch_greedy(const int32_t *A, int32_t n, int32_t *tau, int32_t *sigma,
+                         hipStream_t s);
+hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, int32_t *flag,
+                                 hipStream_t s);
+hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t n, hipStream_t s);
+hipError_t launch_build_w(const int32_t *A, const int32_t *tau, int32_t n, int32_t *W, int32_t *d,
+                          int64_t *f0, hipStream_t s);
+hipError_t launch_scan_rows(const Instance &I, hipStream_t s);
+hipError_t launch_switch_loop(const Instance &I, int64_t max_switches, int grid, hipStream_t s);
+hipError_t launch_export_best(const Instance &I, int64_t *gain_out, int32_t *job_out,
+                              hipStream_t s);
+
+}  // namespace dgs
