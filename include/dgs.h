@@ -58,6 +58,15 @@ typedef enum dgs_status {
 
 /* dgs_options.flags */
 #define DGS_DEVICE_PTRS 0x1u /* benefit, assign_out, init_assign are device pointers */
+#define DGS_PROFILE 0x2u     /* also time each phase with HIP events (dgs_result.phase_ms) */
+
+/* dgs_result.phase_ms indices (filled only with DGS_PROFILE) */
+#define DGS_PHASE_RANGE 0  /* value-range check of the benefit matrix */
+#define DGS_PHASE_INIT 1   /* greedy start (Section 3.1), or loading init_assign */
+#define DGS_PHASE_LAYOUT 2 /* transpose + assignment-ordered working matrix */
+#define DGS_PHASE_SCAN 3   /* difference evaluation of every agent (Algorithm 2) */
+#define DGS_PHASE_SWITCH 4 /* switching phase until no improving switch is left */
+#define DGS_NUM_PHASES 5
 
 typedef struct dgs_options {
     /* Stop after this many switches (< 0: run to the end).  The paper's
@@ -78,7 +87,9 @@ typedef struct dgs_result {
     int64_t initial_benefit; /* f of the start assignment */
     int64_t total_benefit;   /* f of the returned assignment */
     int64_t switches;        /* number of 2-exchanges applied */
+    int64_t rescans;         /* full re-evaluations of agents during switching */
     float device_ms;         /* device time of the solve (HIP events) */
+    float phase_ms[DGS_NUM_PHASES]; /* per-phase device time (DGS_PROFILE only, else 0) */
 } dgs_result;
 
 /* Solve one instance with default options (greedy start, run to the end).

@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(HERE, "libdgs.so")
 
 DGS_OK, DGS_E_INVAL, DGS_E_RANGE, DGS_E_NOMEM, DGS_E_DEVICE, DGS_E_AGAIN = range(6)
 DGS_DEVICE_PTRS = 0x1
+DGS_PROFILE = 0x2
+PHASES = ("range", "init", "layout", "scan", "switch")
 MAX_ABS_BENEFIT = (1 << 29) - 1
 
 # Every symbol include/dgs.h declares.
@@ -52,11 +54,15 @@ class Result(ctypes.Structure):
     _fields_ = [("initial_benefit", ctypes.c_int64),
                 ("total_benefit", ctypes.c_int64),
                 ("switches", ctypes.c_int64),
-                ("device_ms", ctypes.c_float)]
+                ("rescans", ctypes.c_int64),
+                ("device_ms", ctypes.c_float),
+                ("phase_ms", ctypes.c_float * 5)]
 
     def as_dict(self):
         return dict(initial_benefit=int(self.initial_benefit), total_benefit=int(self.total_benefit),
-                    switches=int(self.switches), device_ms=float(self.device_ms))
+                    switches=int(self.switches), rescans=int(self.rescans),
+                    device_ms=float(self.device_ms),
+                    phase_ms={p: float(self.phase_ms[i]) for i, p in enumerate(PHASES)})
 
 
 class ServerConfig(ctypes.Structure):
@@ -141,17 +147,19 @@ def _torch_stream_ptr():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def solve(A, init=None, max_switches: int = -1):
+def solve(A, init=None, max_switches: int = -1, profile: bool = False):
     """Run DGS on one instance.
 
     A: n x n int32 benefit matrix (numpy / CPU tensor, or a ROCm tensor).
     init: optional start permutation (same kind of memory as A).
     Returns (tau, result) with tau[i] the job of agent i (numpy for host
     inputs, a device tensor for device inputs) and result a dict.
+    profile: also time each phase with HIP events (result["phase_ms"]).
     """
     L = lib()
     n = _square_n(A)
-    opt = Options(max_switches=int(max_switches), init_assign=None, flags=0, stream=None)
+    extra = DGS_PROFILE if profile else 0
+    opt = Options(max_switches=int(max_switches), init_assign=None, flags=extra, stream=None)
     res = Result()
     if _is_device_tensor(A):
         import torch
@@ -162,7 +170,7 @@ def solve(A, init=None, max_switches: int = -1):
         if init is not None:
             keep = init.to(device=A.device, dtype=torch.int32).contiguous()
             opt.init_assign = keep.data_ptr()
-        opt.flags = DGS_DEVICE_PTRS
+        opt.flags = DGS_DEVICE_PTRS | extra
         opt.stream = _torch_stream_ptr()
         st = L.dgs_solve_ex(A.data_ptr(), n, out.data_ptr(), ctypes.byref(opt), ctypes.byref(res))
         _check(st, "dgs_solve_ex")

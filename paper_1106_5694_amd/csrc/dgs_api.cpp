@@ -102,6 +102,7 @@ struct Workspace {
     size_t vec_bytes = 0;
     int64_t *host_stats = nullptr;  // pinned: stats[8] then flags[4] (as int64)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ph[DGS_NUM_PHASES + 1] = {};  // phase boundaries (DGS_PROFILE)
 };
 
 std::mutex g_ws_mu;
@@ -111,7 +112,7 @@ std::multimap<int32_t, Workspace *> g_ws_free;
 // 256-byte boundary; vec_layout() is the single source of the offsets used
 // both to size the allocation and to carve it.
 struct VecLayout {
-    size_t tau, sigma, d, bc, bk, bb, recs, barrier, stats, flags, total;
+    size_t tau, sigma, d, bc, bk, bb, recs, barrier, stats, flags, words, replica, total;
 };
 
 VecLayout vec_layout(int32_t n, int grid) {
@@ -132,6 +133,9 @@ VecLayout vec_layout(int32_t n, int grid) {
     L.barrier = take(256);
     L.stats = take(8 * sizeof(int64_t));
     L.flags = take(4 * sizeof(int32_t));
+    const bool ex = n >= 2 && n <= kSwitchExMaxN;
+    L.words = take(ex ? switch_ex_word_bytes(n) : 0);
+    L.replica = take(ex ? switch_ex_replica_bytes(n) : 0);
     L.total = off;
     return L;
 }
@@ -145,6 +149,8 @@ void free_ws(Workspace *w) {
     if (w->host_stats) (void)hipHostFree(w->host_stats);
     if (w->ev0) (void)hipEventDestroy(w->ev0);
     if (w->ev1) (void)hipEventDestroy(w->ev1);
+    for (auto &e : w->ph)
+        if (e) (void)hipEventDestroy(e);
     delete w;
 }
 
@@ -178,7 +184,9 @@ dgs_status alloc_ws(int32_t n, bool need_acopy, Workspace **out) {
     if (hipMalloc((void **)&w->vec, w->vec_bytes) != hipSuccess) return fail("vectors");
     if (hipHostMalloc((void **)&w->host_stats, 16 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
         return fail("pinned stats");
-    if (hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess) {
+    bool ev_ok = hipEventCreate(&w->ev0) == hipSuccess && hipEventCreate(&w->ev1) == hipSuccess;
+    for (auto &e : w->ph) ev_ok = ev_ok && hipEventCreate(&e) == hipSuccess;
+    if (!ev_ok) {
         set_error("hipEventCreate failed");
         free_ws(w);
         return DGS_E_DEVICE;
@@ -211,6 +219,8 @@ Instance carve(Workspace *w, const int32_t *A, int32_t n, int grid) {
     I.barrier = (uint32_t *)(p + L.barrier);
     I.stats = (int64_t *)(p + L.stats);
     I.flags = (int32_t *)(p + L.flags);
+    I.words = p + L.words;
+    I.replica = p + L.replica;
     return I;
 }
 
@@ -248,6 +258,7 @@ struct Call {
     const int32_t *assign_in;  // start (solve) or the assignment to evaluate
     int64_t max_switches;
     bool dev;
+    bool profile;
     hipStream_t stream;
 };
 
@@ -279,10 +290,13 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     if (!c.dev) DGS_HIP(hipMemcpyAsync(w->acopy, c.benefit, mat, hipMemcpyHostToDevice, s));
 
     DGS_HIP(hipEventRecord(w->ev0, s));
+    auto mark = [&](int i) { return c.profile ? hipEventRecord(w->ph[i], s) : hipSuccess; };
     DGS_HIP(hipMemsetAsync(I.barrier, 0, 256, s));
     DGS_HIP(hipMemsetAsync(I.stats, 0, 8 * sizeof(int64_t), s));
     DGS_HIP(hipMemsetAsync(I.flags, 0, 4 * sizeof(int32_t), s));
+    DGS_HIP(mark(DGS_PHASE_RANGE));
     DGS_HIP(launch_range_check(A, (int64_t)n * n, I.flags, s));
+    DGS_HIP(mark(DGS_PHASE_INIT));
     if (c.assign_in) {
         DGS_HIP(hipMemcpyAsync(I.tau, c.assign_in, (size_t)n * 4,
                                c.dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
@@ -290,16 +304,27 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     } else {
         DGS_HIP(launch_greedy(A, n, I.tau, I.sigma, s));
     }
+    DGS_HIP(mark(DGS_PHASE_LAYOUT));
     DGS_HIP(launch_transpose(A, I.AT, n, s));
     DGS_HIP(launch_build_w(A, I.tau, n, I.W, I.d, I.stats + 2, s));
+    DGS_HIP(mark(DGS_PHASE_SCAN));
     DGS_HIP(launch_scan_rows(I, s));
+    DGS_HIP(mark(DGS_PHASE_SWITCH));
     if (mode == Mode::Solve) {
-        // The loop exits at once when the range check failed.
+        // The loops exit at once when the range check failed.  n = 1 has no
+        // exchange at all.
         std::lock_guard<std::mutex> lk(g_ctx.loop_mu);
-        DGS_HIP(launch_switch_loop(I, c.max_switches, grid, s));
+        if (n >= 2 && n <= kSwitchExMaxN) {
+            // stale round tags must not match rounds 0 and 1
+            DGS_HIP(hipMemsetAsync(I.words, 0xFF, switch_ex_word_bytes(n), s));
+            DGS_HIP(launch_switch_ex(I, c.max_switches, I.words, I.replica, I.flags + 2, s));
+        } else if (n > kSwitchExMaxN) {
+            DGS_HIP(launch_switch_loop(I, c.max_switches, grid, s));
+        }
     } else {
         DGS_HIP(launch_export_best(I, gain_out, job_out, s));
     }
+    DGS_HIP(mark(DGS_NUM_PHASES));
     DGS_HIP(hipEventRecord(w->ev1, s));
     DGS_HIP(hipMemcpyAsync(w->host_stats, I.stats, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DGS_HIP(hipMemcpyAsync(w->host_stats + 8, I.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -313,6 +338,10 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         set_error("init_assign is not a permutation of 0..n-1");
         return DGS_E_INVAL;
     }
+    if (flags[2]) {
+        set_error("switching loop: a workgroup wait exceeded its limit");
+        return DGS_E_DEVICE;
+    }
     if (mode == Mode::Solve) {
         DGS_HIP(hipMemcpyAsync(assign_out, I.tau, (size_t)n * 4,
                                c.dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
@@ -325,7 +354,13 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         res->initial_benefit = hs[2];
         res->total_benefit = hs[2] + hs[1];
         res->switches = hs[0];
+        res->rescans = hs[3];
         res->device_ms = ms;
+        for (int i = 0; i < DGS_NUM_PHASES; ++i) {
+            float pm = 0.f;
+            if (c.profile) DGS_HIP(hipEventElapsedTime(&pm, w->ph[i], w->ph[i + 1]));
+            res->phase_ms[i] = pm;
+        }
     }
     return DGS_OK;
 }
@@ -377,6 +412,7 @@ dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out, 
     c.assign_in = opt ? opt->init_assign : nullptr;
     c.max_switches = opt ? opt->max_switches : -1;
     c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
+    c.profile = opt && (opt->flags & DGS_PROFILE);
     c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
     return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
 }
@@ -401,6 +437,7 @@ dgs_status dgs_diff_eval(const int32_t *benefit, int32_t n, const int32_t *assig
     c.assign_in = assign;
     c.max_switches = 0;
     c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
+    c.profile = opt && (opt->flags & DGS_PROFILE);
     c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
     if (c.dev) return run_instance(c, Mode::DiffEval, nullptr, gain_out, job_out, res);
     // host outputs: evaluate into device buffers, then copy
@@ -448,6 +485,7 @@ dgs_status dgs_solve_batched(int32_t count, const int32_t *const *benefits, cons
         c.assign_in = nullptr;
         c.max_switches = opt ? opt->max_switches : -1;
         c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
+        c.profile = opt && (opt->flags & DGS_PROFILE);
         c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
         st = run_instance(c, Mode::Solve, assign_outs[b], nullptr, nullptr, results ? &results[b] : nullptr);
         if (st != DGS_OK) return st;

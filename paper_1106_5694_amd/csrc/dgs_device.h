@@ -1,0 +1,126 @@
+// Device helpers shared by the gfx950 kernels: packed keys and wave64 /
+// workgroup reductions.  Included by .hip sources only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dgs_internal.h"
+
+namespace dgs {
+namespace dev {
+
+// ---- packed keys -----------------------------------------------------------
+// key(g, idx): unsigned order == (g ascending, idx descending).  Key 0 is
+// "no candidate": a real gain is > -2^31, so its biased high word is > 0.
+__device__ __forceinline__ u64 mk_key(int g, int idx) {
+    return ((u64)((uint32_t)g ^ 0x80000000u) << 32) | (u64)(~(uint32_t)idx);
+}
+__device__ __forceinline__ int key_gain(u64 k) { return (int)((uint32_t)(k >> 32) ^ 0x80000000u); }
+__device__ __forceinline__ int key_index(u64 k) { return (int)(~(uint32_t)k); }
+
+__device__ __forceinline__ u64 umax64(u64 a, u64 b) { return a > b ? a : b; }
+__device__ __forceinline__ u64 umin64(u64 a, u64 b) { return a < b ? a : b; }
+
+__device__ __forceinline__ u64 shfl_xor64(u64 v, int mask) {
+    int lo = __shfl_xor((int)(uint32_t)v, mask, 64);
+    int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
+    return ((u64)(uint32_t)hi << 32) | (u64)(uint32_t)lo;
+}
+
+// Top-2 of a set of unique keys (0 = empty slot).
+__device__ __forceinline__ void top2_push(u64 &b1, u64 &b2, u64 k) {
+    u64 lo = umin64(b1, k);
+    b1 = umax64(b1, k);
+    b2 = umax64(b2, lo);
+}
+__device__ __forceinline__ void top2_merge(u64 &a1, u64 &a2, u64 b1, u64 b2) {
+    u64 lo = umin64(a1, b1);
+    a1 = umax64(a1, b1);
+    a2 = umax64(umax64(a2, b2), lo);
+}
+
+// Top-2 with the partner agent of the best entry.
+struct Best2 {
+    u64 k1, k2;
+    int c1;
+};
+__device__ __forceinline__ void best2_push(Best2 &a, u64 k, int c) {
+    if (k > a.k1) {
+        a.k2 = a.k1;
+        a.k1 = k;
+        a.c1 = c;
+    } else {
+        a.k2 = umax64(a.k2, k);
+    }
+}
+__device__ __forceinline__ void best2_merge(Best2 &a, u64 k1, u64 k2, int c1) {
+    if (k1 > a.k1) {
+        a.k2 = umax64(a.k1, k2);
+        a.k1 = k1;
+        a.c1 = c1;
+    } else {
+        a.k2 = umax64(a.k2, k1);
+    }
+}
+
+// Block reductions over BLOCK threads (BLOCK a multiple of 64).  `lds`
+// holds at least 3 * BLOCK / 64 u64.  Every thread gets the result.
+template <int BLOCK>
+__device__ u64 block_max(u64 v, u64 *lds) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = umax64(v, shfl_xor64(v, m));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    u64 r = lds[0];
+#pragma unroll
+    for (int i = 1; i < BLOCK / 64; ++i) r = umax64(r, lds[i]);
+    return r;
+}
+
+template <int BLOCK>
+__device__ void block_top2(u64 &b1, u64 &b2, u64 *lds) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) top2_merge(b1, b2, shfl_xor64(b1, m), shfl_xor64(b2, m));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        lds[2 * w] = b1;
+        lds[2 * w + 1] = b2;
+    }
+    __syncthreads();
+    b1 = lds[0];
+    b2 = lds[1];
+#pragma unroll
+    for (int i = 1; i < BLOCK / 64; ++i) top2_merge(b1, b2, lds[2 * i], lds[2 * i + 1]);
+}
+
+template <int BLOCK>
+__device__ void block_best2(Best2 &a, u64 *lds) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        u64 o1 = shfl_xor64(a.k1, m);
+        u64 o2 = shfl_xor64(a.k2, m);
+        int oc = __shfl_xor(a.c1, m, 64);
+        best2_merge(a, o1, o2, oc);
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        lds[3 * w] = a.k1;
+        lds[3 * w + 1] = a.k2;
+        lds[3 * w + 2] = (u64)(uint32_t)a.c1;
+    }
+    __syncthreads();
+    a.k1 = lds[0];
+    a.k2 = lds[1];
+    a.c1 = (int)(uint32_t)lds[2];
+#pragma unroll
+    for (int i = 1; i < BLOCK / 64; ++i) best2_merge(a, lds[3 * i], lds[3 * i + 1], (int)(uint32_t)lds[3 * i + 2]);
+}
+
+
+}  // namespace dev
+}  // namespace dgs

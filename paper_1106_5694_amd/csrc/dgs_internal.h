@@ -35,8 +35,10 @@ struct Instance {
     // scratch for the switch loop and small reductions
     void *recs = nullptr;        // 2 x grid records
     uint32_t *barrier = nullptr; // grid barrier counter
-    int64_t *stats = nullptr;    // [0] switches, [1] gain sum, [2] f0, [3] rescans
-    int32_t *flags = nullptr;    // [0] range error, [1] permutation error
+    int64_t *stats = nullptr;    // [0] switches, [1] gain sum, [2] f0, [3] re-evaluations, [4] stalls
+    int32_t *flags = nullptr;    // [0] range error, [1] permutation error, [2] wait timed out
+    void *words = nullptr;       // exchange words of the switching loop
+    void *replica = nullptr;     // private replicas of the switching loop (large n)
 };
 
 size_t loop_record_bytes();
@@ -52,6 +54,15 @@ hipError_t launch_build_w(const int32_t *A, const int32_t *tau, int32_t n, int32
                           int64_t *f0, hipStream_t s);
 hipError_t launch_scan_rows(const Instance &I, hipStream_t s);
 hipError_t launch_switch_loop(const Instance &I, int64_t max_switches, int grid, hipStream_t s);
+// Switching loop with fence-free exchange (dgs_switch.hip), for 2 <= n <= kSwitchExMaxN.
+constexpr int kSwitchExMaxN = 65535;
+int switch_ex_grid(int n);
+size_t switch_ex_word_bytes(int n);
+bool switch_ex_lds_replica(int n);
+size_t switch_ex_replica_bytes(int n);
+hipError_t launch_switch_ex(const Instance &I, int64_t max_switches, void *words, void *replica, int32_t *err,
+                            hipStream_t s);
+
 hipError_t launch_export_best(const Instance &I, int64_t *gain_out, int32_t *job_out,
                               hipStream_t s);
 
