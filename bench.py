@@ -143,8 +143,9 @@ def main() -> int:
         phases[p] = {"ms": round(ms, 4), "algorithmic_bytes": byts, "GB/s": round(gbs, 1),
                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     dominant = max(phases, key=lambda p: phases[p]["ms"])
-    kernel_names = {"range": "k_range_check", "init": "k_greedy_wg", "layout": "k_transpose+k_build_w",
-                    "scan": "k_scan_rows", "switch": "k_switch_loop"}
+    kernel_names = {"range": "k_range_check", "init": "k_greedy_topk+k_greedy_resolve",
+                    "layout": "k_transpose+k_build_w", "scan": "k_scan_pairs+k_scan_reduce",
+                    "switch": "k_switch_ex"}
     d = phases[dominant]
     roofline = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["hbm_frac"], "traffic": None, "kernel": kernel_names[dominant],
@@ -176,6 +177,9 @@ def main() -> int:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(A, S)
     print(json.dumps(line), flush=True)
+    del Ad, tau
+    torch.cuda.synchronize()
+    dgs.release_cached()
     return 0
 
 

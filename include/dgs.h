@@ -127,7 +127,14 @@ dgs_status dgs_diff_eval(const int32_t *benefit, int32_t n, const int32_t *assig
                          int64_t *gain_out, int32_t *job_out, const dgs_options *opt,
                          dgs_result *res);
 
-/* ---- Serving: continuous batching of periodic LSAP requests ---------- */
+/* ---- Serving: continuous batching of periodic LSAP requests ---------- *
+ * A stream of independent instances (the periodic re-assignment setting of
+ * Section 1) solved as they arrive.  Requests with n <= 2048 that are waiting
+ * when the batch worker is free are solved together in one batched launch
+ * (as dgs_solve_batched); larger requests run concurrently on their own
+ * streams, each admitted when its footprint fits the memory budget and its
+ * switching loop fits the compute units left free by the running ones.
+ * Every result equals dgs_solve on the same instance. */
 
 typedef struct dgs_server dgs_server;
 
@@ -182,6 +189,11 @@ const char *dgs_last_error(void);
 
 /* Library version string. */
 const char *dgs_version(void);
+
+/* Free the device memory the library caches between calls (workspaces of
+ * finished solves).  Safe to call at any time; solves in progress keep
+ * their own workspaces.  Later calls allocate again as needed. */
+void dgs_release_cached(void);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,7 @@ EXPORTS = (
     "dgs_solve", "dgs_solve_ex", "dgs_solve_batched", "dgs_diff_eval",
     "dgs_server_footprint", "dgs_server_create", "dgs_server_submit", "dgs_server_poll",
     "dgs_server_wait", "dgs_server_stats_get", "dgs_server_destroy",
-    "dgs_status_string", "dgs_last_error", "dgs_version",
+    "dgs_status_string", "dgs_last_error", "dgs_version", "dgs_release_cached",
 )
 
 
@@ -108,6 +108,7 @@ def lib() -> ctypes.CDLL:
     L.dgs_status_string.restype = ctypes.c_char_p
     L.dgs_last_error.restype = ctypes.c_char_p
     L.dgs_version.restype = ctypes.c_char_p
+    L.dgs_release_cached.restype = None
     for name in ("dgs_solve", "dgs_solve_ex", "dgs_solve_batched", "dgs_diff_eval", "dgs_server_create",
                  "dgs_server_submit", "dgs_server_poll", "dgs_server_wait", "dgs_server_stats_get"):
         getattr(L, name).restype = ctypes.c_int
@@ -238,6 +239,11 @@ def solve_batched(As: Sequence, max_switches: int = -1):
     st = L.dgs_solve_batched(count, bptr, ns.ctypes.data, optr, results, ctypes.byref(opt))
     _check(st, "dgs_solve_batched")
     return outs, [r.as_dict() for r in results]
+
+
+def release_cached() -> None:
+    """Free the device memory the library caches between calls."""
+    lib().dgs_release_cached()
 
 
 def server_footprint(n: int) -> int:

@@ -112,7 +112,7 @@ std::multimap<int32_t, Workspace *> g_ws_free;
 // 256-byte boundary; vec_layout() is the single source of the offsets used
 // both to size the allocation and to carve it.
 struct VecLayout {
-    size_t tau, sigma, d, bc, bk, bb, recs, barrier, stats, flags, words, replica, total;
+    size_t tau, sigma, d, bc, bk, bb, lists, recs, barrier, stats, flags, words, replica, greedy, scan, total;
 };
 
 VecLayout vec_layout(int32_t n, int grid) {
@@ -129,6 +129,7 @@ VecLayout vec_layout(int32_t n, int grid) {
     L.bc = take((size_t)n * 4);
     L.bk = take((size_t)n * 8);
     L.bb = take((size_t)n * 8);
+    L.lists = take((size_t)n * 8 * kScanListLen);
     L.recs = take(2 * (size_t)grid * loop_record_bytes());
     L.barrier = take(256);
     L.stats = take(8 * sizeof(int64_t));
@@ -136,6 +137,8 @@ VecLayout vec_layout(int32_t n, int grid) {
     const bool ex = n >= 2 && n <= kSwitchExMaxN;
     L.words = take(ex ? switch_ex_word_bytes(n) : 0);
     L.replica = take(ex ? switch_ex_replica_bytes(n) : 0);
+    L.greedy = take(greedy_scratch_bytes(n));
+    L.scan = take(scan_pairs_scratch_bytes(n));
     L.total = off;
     return L;
 }
@@ -215,12 +218,15 @@ Instance carve(Workspace *w, const int32_t *A, int32_t n, int grid) {
     I.bc = (int32_t *)(p + L.bc);
     I.bk = (u64 *)(p + L.bk);
     I.bb = (u64 *)(p + L.bb);
+    I.lists = (u64 *)(p + L.lists);
     I.recs = p + L.recs;
     I.barrier = (uint32_t *)(p + L.barrier);
     I.stats = (int64_t *)(p + L.stats);
     I.flags = (int32_t *)(p + L.flags);
     I.words = p + L.words;
     I.replica = p + L.replica;
+    I.greedy = p + L.greedy;
+    I.scan = p + L.scan;
     return I;
 }
 
@@ -259,6 +265,7 @@ struct Call {
     int64_t max_switches;
     bool dev;
     bool profile;
+    bool coop = true;  // cooperative switching launch (else the caller owns co-residency)
     hipStream_t stream;
 };
 
@@ -302,24 +309,30 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
                                c.dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         DGS_HIP(launch_invert_checked(I.tau, n, I.sigma, I.flags + 1, s));
     } else {
-        DGS_HIP(launch_greedy(A, n, I.tau, I.sigma, s));
+        DGS_HIP(launch_greedy_rounds(A, n, I.tau, I.sigma, I.greedy, I.flags + 2, s));
     }
     DGS_HIP(mark(DGS_PHASE_LAYOUT));
     DGS_HIP(launch_transpose(A, I.AT, n, s));
     DGS_HIP(launch_build_w(A, I.tau, n, I.W, I.d, I.stats + 2, s));
     DGS_HIP(mark(DGS_PHASE_SCAN));
-    DGS_HIP(launch_scan_rows(I, s));
+    DGS_HIP(launch_scan_pairs(I, I.scan, s));
     DGS_HIP(mark(DGS_PHASE_SWITCH));
     if (mode == Mode::Solve) {
         // The loops exit at once when the range check failed.  n = 1 has no
-        // exchange at all.
-        std::lock_guard<std::mutex> lk(g_ctx.loop_mu);
+        // exchange at all.  Cooperative switching loops of concurrent calls
+        // run one at a time (each needs its whole grid resident).
+        std::unique_lock<std::mutex> lk(g_ctx.loop_mu, std::defer_lock);
+        if (c.coop) lk.lock();
         if (n >= 2 && n <= kSwitchExMaxN) {
             // stale round tags must not match rounds 0 and 1
             DGS_HIP(hipMemsetAsync(I.words, 0xFF, switch_ex_word_bytes(n), s));
-            DGS_HIP(launch_switch_ex(I, c.max_switches, I.words, I.replica, I.flags + 2, s));
+            DGS_HIP(launch_switch_ex(I, c.max_switches, I.words, I.replica, I.flags + 2, c.coop, s));
         } else if (n > kSwitchExMaxN) {
             DGS_HIP(launch_switch_loop(I, c.max_switches, grid, s));
+        }
+        if (c.coop) {
+            DGS_HIP(hipEventRecord(w->ev1, s));
+            DGS_HIP(hipEventSynchronize(w->ev1));
         }
     } else {
         DGS_HIP(launch_export_best(I, gain_out, job_out, s));
@@ -339,7 +352,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         return DGS_E_INVAL;
     }
     if (flags[2]) {
-        set_error("switching loop: a workgroup wait exceeded its limit");
+        set_error("internal device check failed (code %d)", flags[2]);
         return DGS_E_DEVICE;
     }
     if (mode == Mode::Solve) {
@@ -365,6 +378,195 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     return DGS_OK;
 }
 
+// ---- batched solves ------------------------------------------------------------------
+// Instances with n <= kBatchMaxN run in one persistent launch (one workgroup
+// per instance, largest first); larger ones run one after another through
+// the single-instance path.  The device arena is cached between calls.
+
+struct BatchCall {
+    int32_t count;
+    const int32_t *const *benefits;
+    const int32_t *ns;
+    int32_t *const *outs;
+    dgs_result *results;
+    int64_t max_switches;
+    bool dev;
+    bool profile;
+    int grid_cap = 0;  // > 0: at most this many workgroups (the server reserves the rest)
+    hipStream_t stream;
+};
+
+struct BatchArena {
+    std::mutex mu;
+    char *dev = nullptr;
+    size_t bytes = 0;
+    char *host = nullptr;  // pinned staging for items / order / results
+    size_t host_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+BatchArena g_batch;
+
+int g_batch_block = 256;  // workgroup size of the batched solver (autotuned)
+
+dgs_status batch_reserve(size_t dev_bytes, size_t host_bytes) {
+    if (dev_bytes > g_batch.bytes) {
+        if (g_batch.dev) (void)hipFree(g_batch.dev);
+        g_batch.dev = nullptr;
+        g_batch.bytes = 0;
+        if (hipMalloc((void **)&g_batch.dev, dev_bytes) != hipSuccess) {
+            set_error("device allocation of %zu bytes for a batch failed", dev_bytes);
+            return DGS_E_NOMEM;
+        }
+        g_batch.bytes = dev_bytes;
+    }
+    if (host_bytes > g_batch.host_bytes) {
+        if (g_batch.host) (void)hipHostFree(g_batch.host);
+        g_batch.host = nullptr;
+        g_batch.host_bytes = 0;
+        if (hipHostMalloc((void **)&g_batch.host, host_bytes, hipHostMallocDefault) != hipSuccess) {
+            set_error("pinned allocation of %zu bytes for a batch failed", host_bytes);
+            return DGS_E_NOMEM;
+        }
+        g_batch.host_bytes = host_bytes;
+    }
+    if (!g_batch.ev0) {
+        if (hipEventCreate(&g_batch.ev0) != hipSuccess || hipEventCreate(&g_batch.ev1) != hipSuccess) {
+            set_error("hipEventCreate failed");
+            return DGS_E_DEVICE;
+        }
+    }
+    return DGS_OK;
+}
+
+dgs_status run_batch(const BatchCall &c) {
+    hipStream_t s = c.stream;
+    std::vector<int32_t> small, large;
+    for (int32_t b = 0; b < c.count; ++b) (c.ns[b] <= kBatchMaxN ? small : large).push_back(b);
+    // largest first: the longest instances start first (LPT order)
+    std::stable_sort(small.begin(), small.end(), [&](int32_t x, int32_t y) { return c.ns[x] > c.ns[y]; });
+    const size_t m = small.size();
+    if (m) {
+        std::lock_guard<std::mutex> lk(g_batch.mu);
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        size_t mat = 0, vec = 0;
+        for (int32_t b : small) {
+            mat += al((size_t)c.ns[b] * c.ns[b] * 4);
+            vec += al((size_t)c.ns[b] * 4);
+        }
+        size_t lists = 0;
+        for (int32_t b : small) lists += al((size_t)c.ns[b] * 16);
+        const size_t items_b = al(m * sizeof(BatchItem)), order_b = al(m * 4), res_b = al(m * 5 * 8);
+        const size_t dev_bytes = (c.dev ? 0 : mat) + mat + lists + (c.dev ? 0 : vec) + items_b + order_b + res_b + 256;
+        const size_t host_bytes = items_b + order_b + res_b;
+        dgs_status st = batch_reserve(dev_bytes, host_bytes);
+        if (st != DGS_OK) return st;
+        char *p = g_batch.dev;
+        char *acopy = nullptr, *tauo = nullptr;
+        if (!c.dev) {
+            acopy = p;
+            p += mat;
+        }
+        char *at = p;
+        p += mat;
+        char *lst = p;
+        p += lists;
+        if (!c.dev) {
+            tauo = p;
+            p += vec;
+        }
+        BatchItem *d_items = (BatchItem *)p;
+        p += items_b;
+        int32_t *d_order = (int32_t *)p;
+        p += order_b;
+        int64_t *d_res = (int64_t *)p;
+        p += res_b;
+        int32_t *d_queue = (int32_t *)p;
+        BatchItem *h_items = (BatchItem *)g_batch.host;
+        int32_t *h_order = (int32_t *)(g_batch.host + items_b);
+        int64_t *h_res = (int64_t *)(g_batch.host + items_b + order_b);
+        size_t om = 0, ov = 0, ol = 0;
+        for (size_t x = 0; x < m; ++x) {
+            const int32_t b = small[x];
+            const int32_t n = c.ns[b];
+            BatchItem &it = h_items[x];
+            if (c.dev) {
+                it.A = c.benefits[b];
+                it.tau = c.outs[b];
+            } else {
+                DGS_HIP(hipMemcpyAsync(acopy + om, c.benefits[b], (size_t)n * n * 4, hipMemcpyHostToDevice, s));
+                it.A = (const int32_t *)(acopy + om);
+                it.tau = (int32_t *)(tauo + ov);
+                ov += al((size_t)n * 4);
+            }
+            it.AT = (int32_t *)(at + om);
+            it.lists = (u64 *)(lst + ol);
+            it.res = d_res + 5 * x;
+            it.n = n;
+            it.pad = 0;
+            om += al((size_t)n * n * 4);
+            ol += al((size_t)n * 16);
+            h_order[x] = (int32_t)x;
+        }
+        DGS_HIP(hipMemcpyAsync(d_items, h_items, m * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+        DGS_HIP(hipMemcpyAsync(d_order, h_order, m * 4, hipMemcpyHostToDevice, s));
+        DGS_HIP(hipMemsetAsync(d_queue, 0, 4, s));
+        const int limit = batch_grid_limit(g_batch_block);
+        if (limit < 1) {
+            set_error("cannot size the batched solver's grid");
+            return DGS_E_DEVICE;
+        }
+        int grid = (int)std::min<size_t>(m, (size_t)limit);
+        if (c.grid_cap > 0) grid = std::min(grid, c.grid_cap);
+        DGS_HIP(hipEventRecord(g_batch.ev0, s));
+        DGS_HIP(launch_batch(d_items, d_order, (int)m, d_queue, c.max_switches, g_batch_block, grid, s));
+        DGS_HIP(hipEventRecord(g_batch.ev1, s));
+        DGS_HIP(hipMemcpyAsync(h_res, d_res, m * 5 * 8, hipMemcpyDeviceToHost, s));
+        DGS_HIP(hipStreamSynchronize(s));
+        for (size_t x = 0; x < m; ++x) {
+            if (h_res[5 * x + 4] != DGS_OK) {
+                set_error("batch instance %d: benefit entry outside [-(2^29-1), 2^29-1]", small[x]);
+                return (dgs_status)h_res[5 * x + 4];
+            }
+        }
+        float ms = 0.f;
+        DGS_HIP(hipEventElapsedTime(&ms, g_batch.ev0, g_batch.ev1));
+        if (!c.dev) {
+            size_t ov2 = 0;
+            for (size_t x = 0; x < m; ++x) {
+                const int32_t b = small[x];
+                DGS_HIP(hipMemcpyAsync(c.outs[b], tauo + ov2, (size_t)c.ns[b] * 4, hipMemcpyDeviceToHost, s));
+                ov2 += al((size_t)c.ns[b] * 4);
+            }
+            DGS_HIP(hipStreamSynchronize(s));
+        }
+        if (c.results) {
+            for (size_t x = 0; x < m; ++x) {
+                dgs_result &r = c.results[small[x]];
+                std::memset(&r, 0, sizeof r);
+                r.initial_benefit = h_res[5 * x];
+                r.total_benefit = h_res[5 * x + 1];
+                r.switches = h_res[5 * x + 2];
+                r.rescans = h_res[5 * x + 3];
+                r.device_ms = ms;  // the whole batched launch
+            }
+        }
+    }
+    for (int32_t b : large) {
+        Call one;
+        one.benefit = c.benefits[b];
+        one.n = c.ns[b];
+        one.assign_in = nullptr;
+        one.max_switches = c.max_switches;
+        one.dev = c.dev;
+        one.profile = c.profile;
+        one.stream = s;
+        dgs_status st = run_instance(one, Mode::Solve, c.outs[b], nullptr, nullptr,
+                                     c.results ? &c.results[b] : nullptr);
+        if (st != DGS_OK) return st;
+    }
+    return DGS_OK;
+}
+
 dgs_status check_common(const int32_t *benefit, int32_t n, const void *out) {
     if (!benefit || !out) {
         set_error("NULL pointer argument");
@@ -378,6 +580,50 @@ dgs_status check_common(const int32_t *benefit, int32_t n, const void *out) {
 }
 
 }  // namespace
+
+int device_cus() {
+    int cus = 0;
+    if (ensure_context() != DGS_OK) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g_ctx.device) != hipSuccess) return 0;
+    return cus;
+}
+
+dgs_status solve_internal(const int32_t *benefit, int32_t n, int32_t *assign_out, int64_t max_switches, bool dev,
+                          bool coop, hipStream_t s, dgs_result *res) {
+    dgs_status st = check_common(benefit, n, assign_out);
+    if (st != DGS_OK) return st;
+    if ((st = ensure_context()) != DGS_OK) return st;
+    Call c;
+    c.benefit = benefit;
+    c.n = n;
+    c.assign_in = nullptr;
+    c.max_switches = max_switches;
+    c.dev = dev;
+    c.profile = false;
+    c.coop = coop;
+    c.stream = s ? s : g_ctx.stream;
+    return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
+}
+
+dgs_status solve_batch_internal(int32_t count, const int32_t *const *benefits, const int32_t *ns,
+                                int32_t *const *outs, dgs_result *results, int64_t max_switches, int grid_cap,
+                                hipStream_t s) {
+    dgs_status st = ensure_context();
+    if (st != DGS_OK) return st;
+    BatchCall c;
+    c.count = count;
+    c.benefits = benefits;
+    c.ns = ns;
+    c.outs = outs;
+    c.results = results;
+    c.max_switches = max_switches;
+    c.dev = false;
+    c.profile = false;
+    c.grid_cap = grid_cap;
+    c.stream = s ? s : g_ctx.stream;
+    return run_batch(c);
+}
+
 }  // namespace dgs
 
 using namespace dgs;
@@ -399,6 +645,21 @@ const char *dgs_status_string(dgs_status st) {
 const char *dgs_last_error(void) { return g_last_error.c_str(); }
 
 const char *dgs_version(void) { return "dgs-gfx950 0.1"; }
+
+void dgs_release_cached(void) {
+    std::multimap<int32_t, Workspace *> drop;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        drop.swap(g_ws_free);
+    }
+    for (auto &kv : drop) free_ws(kv.second);
+    std::lock_guard<std::mutex> lk(g_batch.mu);
+    if (g_batch.dev) (void)hipFree(g_batch.dev);
+    if (g_batch.host) (void)hipHostFree(g_batch.host);
+    g_batch.dev = nullptr;
+    g_batch.host = nullptr;
+    g_batch.bytes = g_batch.host_bytes = 0;
+}
 
 dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out, const dgs_options *opt,
                         dgs_result *res) {
@@ -476,21 +737,20 @@ dgs_status dgs_solve_batched(int32_t count, const int32_t *const *benefits, cons
         dgs_status st = check_common(benefits[b], ns[b], assign_outs[b]);
         if (st != DGS_OK) return st;
     }
+    if (count == 0) return DGS_OK;
     dgs_status st = ensure_context();
     if (st != DGS_OK) return st;
-    for (int32_t b = 0; b < count; ++b) {
-        Call c;
-        c.benefit = benefits[b];
-        c.n = ns[b];
-        c.assign_in = nullptr;
-        c.max_switches = opt ? opt->max_switches : -1;
-        c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
-        c.profile = opt && (opt->flags & DGS_PROFILE);
-        c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
-        st = run_instance(c, Mode::Solve, assign_outs[b], nullptr, nullptr, results ? &results[b] : nullptr);
-        if (st != DGS_OK) return st;
-    }
-    return DGS_OK;
+    BatchCall c;
+    c.count = count;
+    c.benefits = benefits;
+    c.ns = ns;
+    c.outs = assign_outs;
+    c.results = results;
+    c.max_switches = opt ? opt->max_switches : -1;
+    c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
+    c.profile = opt && (opt->flags & DGS_PROFILE);
+    c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
+    return run_batch(c);
 }
 
 }  // extern "C"

@@ -1,0 +1,430 @@
+// Batched DGS on gfx950: many independent instances (n <= kBatchMaxN) in one
+// persistent launch.  Workgroups take instances from a device-side queue
+// (largest first) and solve each one alone, end to end, so no data crosses
+// workgroups:
+//   1. greedy start (Section 3.1) with the value-range check fused in: agents
+//      in order; thread t owns columns t, t + BLOCK, ...; one block max per
+//      agent over the free columns (each thread tracks its own columns'
+//      taken flags in registers);
+//   2. transpose AT = A^T through LDS tiles;
+//   3. difference evaluation of every agent (Algorithm 2): a wave stages row
+//      r of A in LDS and scores g(r, c) = a[r][tau(c)] + AT[tau(r)][c]
+//      - d(r) - d(c) for all c; each agent starts with its best exchange and
+//      the second best as its bound;
+//   4. switching (Algorithm 1 as steepest ascent): block max over the
+//      agents' list maxima, apply, update every agent's two changed
+//      candidates, rebuild the two switched agents' lists from the same
+//      values (g(r, c) = g(c, r)), re-evaluate agents whose list ran empty.
+// Results are identical to the single-instance path.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dgs_device.h"
+#include "dgs_internal.h"
+
+namespace dgs {
+namespace {
+
+using namespace dev;
+
+constexpr int kBM = 4;  // candidate list length per agent
+constexpr int kMaxAbsB = 536870911;
+
+// (gain:32 | 0xFFFF - row:16 | job:16): unsigned order = (gain asc, row desc);
+// the job rides along (rows are unique).
+__device__ __forceinline__ u64 wkey(int g, int row, int job) {
+    return ((u64)((uint32_t)g ^ 0x80000000u) << 32) | ((u64)(0xFFFFu - (uint32_t)row) << 16) | (uint32_t)job;
+}
+__device__ __forceinline__ int wrow(u64 k) { return (int)(0xFFFFu - (uint32_t)((k >> 16) & 0xFFFFu)); }
+__device__ __forceinline__ int wjob(u64 k) { return (int)(uint32_t)(k & 0xFFFFu); }
+
+template <int BLOCK>
+struct Red {
+    static constexpr int W = BLOCK / 64;
+};
+
+// Block max of one u64; `slot` alternates between two LDS rows so that one
+// barrier per call suffices.
+template <int BLOCK>
+__device__ __forceinline__ u64 bmax1(u64 v, u64 *red, int &slot) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = umax64(v, shfl_xor64(v, m));
+    u64 *row = red + slot * Red<BLOCK>::W;
+    slot ^= 1;
+    if ((threadIdx.x & 63) == 0) row[threadIdx.x >> 6] = v;
+    __syncthreads();
+    u64 r = row[0];
+#pragma unroll
+    for (int i = 1; i < Red<BLOCK>::W; ++i) r = umax64(r, row[i]);
+    return r;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void btop2(u64 &a1, u64 &a2, u64 *red, int &slot) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) top2_merge(a1, a2, shfl_xor64(a1, m), shfl_xor64(a2, m));
+    u64 *row = red + slot * 2 * Red<BLOCK>::W;
+    slot ^= 1;
+    if ((threadIdx.x & 63) == 0) {
+        row[2 * (threadIdx.x >> 6)] = a1;
+        row[2 * (threadIdx.x >> 6) + 1] = a2;
+    }
+    __syncthreads();
+    a1 = row[0];
+    a2 = row[1];
+#pragma unroll
+    for (int i = 1; i < Red<BLOCK>::W; ++i) top2_merge(a1, a2, row[2 * i], row[2 * i + 1]);
+}
+
+// Unsorted list of kBM exact candidates (0 = empty) plus bound.
+__device__ __forceinline__ u64 lmax(const u64 *L) {
+    u64 m = L[0];
+#pragma unroll
+    for (int i = 1; i < kBM; ++i) m = umax64(m, L[i]);
+    return m;
+}
+__device__ __forceinline__ void ldrop(u64 *L, int j1, int j2) {
+#pragma unroll
+    for (int i = 0; i < kBM; ++i) {
+        const int j = key_index(L[i]);
+        if (L[i] != 0 && (j == j1 || j == j2)) L[i] = 0;
+    }
+}
+__device__ __forceinline__ void linsert(u64 *L, u64 &B, u64 y) {
+    if (y <= B) return;
+    u64 mn = L[0];
+    int mi = 0;
+#pragma unroll
+    for (int i = 1; i < kBM; ++i)
+        if (L[i] < mn) {
+            mn = L[i];
+            mi = i;
+        }
+    if (mn != 0) {
+        if (y < mn) {
+            B = y;
+            return;
+        }
+        B = umax64(B, mn);
+    }
+#pragma unroll
+    for (int i = 0; i < kBM; ++i)
+        if (i == mi) L[i] = y;
+}
+
+// Full evaluation of agent r by one wave (row of A staged in `arow`).
+// Returns top-2 keys (gain, job) over partners c != r in lane 0..63 (all lanes).
+__device__ __forceinline__ void wave_eval_row(const int32_t *A, const int32_t *AT, int n, int r,
+                                              const uint16_t *rt, const int32_t *rd, int32_t *arow, u64 &b1,
+                                              u64 &b2) {
+    const int lane = threadIdx.x & 63;
+    const int32_t *Ar = A + (int64_t)r * n;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // earlier reads of arow are done
+    for (int c = lane; c < n; c += 64) arow[c] = Ar[c];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the row is in LDS for every lane
+    const int32_t *Tr = AT + (int64_t)rt[r] * n;
+    const int dr = rd[r];
+    b1 = 0;
+    b2 = 0;
+    int g2 = INT32_MIN;
+    for (int c = lane; c < n; c += 64) {
+        const int g = (arow[rt[c]] + Tr[c]) - (dr + rd[c]);
+        if (g >= g2 && c != r) {
+            top2_push(b1, b2, mk_key(g, rt[c]));
+            g2 = b2 ? key_gain(b2) : INT32_MIN;
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) top2_merge(b1, b2, shfl_xor64(b1, m), shfl_xor64(b2, m));
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, const int32_t *order, int count,
+                                                        int32_t *queue, int64_t max_switches) {
+    constexpr int RPT = kBatchMaxN / BLOCK;  // agents (and columns) per thread
+    constexpr int NW = BLOCK / 64;
+    __shared__ uint16_t rt[kBatchMaxN];
+    __shared__ uint16_t rs[kBatchMaxN];
+    __shared__ int32_t rd[kBatchMaxN];
+    __shared__ int32_t rowbuf[NW][kBatchMaxN + 64];  // per-wave staged rows / 32 x 65 transpose tiles
+    __shared__ u64 red[4 * NW];
+    __shared__ int s_item;
+    __shared__ int dirty_list[kBatchMaxN];
+    __shared__ int dirty_n;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    int slot = 0;
+
+    for (;;) {
+        if (t == 0) s_item = atomicAdd(queue, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= count) break;
+        const BatchItem I = items[order[it]];
+        const int n = I.n;
+        const int32_t *A = I.A;
+
+        // ---- 1. greedy start + range check -----------------------------------------------
+        bool taken[RPT];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) taken[u] = false;
+        int bad = 0;
+        int64_t f0 = 0;
+        int nv[RPT];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int c = t + u * BLOCK;
+            nv[u] = c < n ? A[c] : 0;
+        }
+        for (int i = 0; i < n; ++i) {
+            int v[RPT];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) v[u] = nv[u];
+            if (i + 1 < n) {
+                const int32_t *Ar = A + (int64_t)(i + 1) * n;
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) {
+                    const int c = t + u * BLOCK;
+                    nv[u] = c < n ? Ar[c] : 0;
+                }
+            }
+            u64 best = 0;
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int c = t + u * BLOCK;
+                if (c < n) {
+                    bad |= (v[u] > kMaxAbsB) | (v[u] < -kMaxAbsB);
+                    if (!taken[u]) best = umax64(best, mk_key(v[u], c));
+                }
+            }
+            best = bmax1<BLOCK>(best, red, slot);
+            const int c = best ? key_index(best) : 0;  // a free column always exists
+            if (c % BLOCK == t) {
+#pragma unroll
+                for (int u = 0; u < RPT; ++u)
+                    if (u == c / BLOCK) taken[u] = true;
+            }
+            if (t == 0) {
+                rt[i] = (uint16_t)c;
+                rs[c] = (uint16_t)i;
+                rd[i] = key_gain(best);
+            }
+            f0 += key_gain(best);
+        }
+        {
+            u64 b = bad ? 1 : 0;
+            b = bmax1<BLOCK>(b, red, slot);
+            bad = (int)b;
+        }
+        if (bad) {
+            if (t == 0) {
+                I.res[4] = DGS_E_RANGE;
+                I.res[0] = I.res[1] = I.res[2] = I.res[3] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+
+        // ---- 2. transpose A -> AT through 64x64 LDS tiles (one tile per wave) ---------------
+        {
+            int32_t *tile = rowbuf[w];  // 32 x 65 ints
+            const int nt = (n + 63) / 64;
+            for (int tt = w; tt < nt * nt; tt += NW) {
+                const int bi = tt / nt, bj = tt % nt;
+                // two passes of 32 rows (a 64 x 32 tile with padding fits the wave's buffer)
+                for (int h = 0; h < 2; ++h) {
+                    for (int rr = 0; rr < 32; ++rr) {
+                        const int row = bi * 64 + h * 32 + rr, col = bj * 64 + lane;
+                        tile[rr * 65 + lane] = (row < n && col < n) ? A[(int64_t)row * n + col] : 0;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    // AT[col][row] for col = bj*64 + cc, row = bi*64 + h*32 + lane (lane < 32)
+                    for (int cc = 0; cc < 64; ++cc) {
+                        const int col = bj * 64 + cc, row = bi * 64 + h * 32 + lane;
+                        if (lane < 32 && col < n && row < n) I.AT[(int64_t)col * n + row] = tile[lane * 65 + cc];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                }
+            }
+        }
+        __syncthreads();
+        __threadfence_block();
+
+        // ---- 3. difference evaluation of every agent -------------------------------------------
+        // wave w evaluates agents w, w + NW, ...; results go to the agents' owner
+        // threads through I.lists (private to this workgroup).
+        for (int r = w; r < n; r += NW) {
+            u64 b1, b2;
+            wave_eval_row(A, I.AT, n, r, rt, rd, rowbuf[w], b1, b2);
+            if (lane == 0) {
+                I.lists[2 * r] = b1;
+                I.lists[2 * r + 1] = b2;
+            }
+        }
+        __syncthreads();
+        u64 L[RPT][kBM];
+        u64 B[RPT];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int r = t + u * BLOCK;
+#pragma unroll
+            for (int i = 0; i < kBM; ++i) L[u][i] = 0;
+            B[u] = 0;
+            if (r < n) {
+                L[u][0] = I.lists[2 * r];
+                B[u] = I.lists[2 * r + 1];
+            }
+        }
+
+        // ---- 4. switching ---------------------------------------------------------------------
+        int64_t S = 0, gsum = 0, rescans = 0;
+        for (;;) {
+            u64 mine = 0;
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int r = t + u * BLOCK;
+                if (r < n) {
+                    const u64 b = lmax(L[u]);
+                    if (b) mine = umax64(mine, wkey(key_gain(b), r, key_index(b)));
+                }
+            }
+            const u64 best = bmax1<BLOCK>(mine, red, slot);
+            const int gw = best ? (int)((uint32_t)(best >> 32) ^ 0x80000000u) : 0;
+            if (best == 0 || gw <= 0 || (max_switches >= 0 && S >= max_switches)) break;
+            const int is = wrow(best), js = wjob(best);
+            const int k = rs[js], j0 = rt[is];
+            const int dis = A[(int64_t)is * n + js];
+            const int dk = A[(int64_t)k * n + j0];
+            // loads of the two changed candidates of every owned agent
+            int a1[RPT], a2[RPT], w1[RPT], w2[RPT], dr[RPT], tr[RPT];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int r = t + u * BLOCK;
+                a1[u] = a2[u] = w1[u] = w2[u] = dr[u] = tr[u] = 0;
+                if (r < n && r != is && r != k) {
+                    tr[u] = rt[r];
+                    dr[u] = rd[r];
+                    a1[u] = I.AT[(int64_t)js * n + r];
+                    a2[u] = I.AT[(int64_t)j0 * n + r];
+                    w1[u] = A[(int64_t)is * n + tr[u]];
+                    w2[u] = A[(int64_t)k * n + tr[u]];
+                }
+            }
+            ++S;
+            gsum += gw;
+            __syncthreads();  // every thread has read rt / rs / rd
+            if (t == 0) {
+                rt[is] = (uint16_t)js;
+                rt[k] = (uint16_t)j0;
+                rs[js] = (uint16_t)is;
+                rs[j0] = (uint16_t)k;
+                rd[is] = dis;
+                rd[k] = dk;
+                dirty_n = 0;
+            }
+            u64 pi1 = 0, pi2 = 0, pk1 = 0, pk2 = 0;  // candidates of agents i* and k
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int r = t + u * BLOCK;
+                if (r >= n) continue;
+                if (r == is) {
+                    top2_push(pk1, pk2, mk_key(-gw, js));
+                    continue;
+                }
+                if (r == k) {
+                    top2_push(pi1, pi2, mk_key(-gw, j0));
+                    continue;
+                }
+                const int g1 = (a1[u] + w1[u]) - (dr[u] + dis);
+                const int g2 = (a2[u] + w2[u]) - (dr[u] + dk);
+                ldrop(L[u], js, j0);
+                linsert(L[u], B[u], mk_key(g1, js));
+                linsert(L[u], B[u], mk_key(g2, j0));
+                top2_push(pi1, pi2, mk_key(g1, tr[u]));
+                top2_push(pk1, pk2, mk_key(g2, tr[u]));
+            }
+            __syncthreads();  // dirty_n reset and replicas visible
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int r = t + u * BLOCK;
+                if (r < n && r != is && r != k && lmax(L[u]) == 0) dirty_list[atomicAdd(&dirty_n, 1)] = r;
+            }
+            btop2<BLOCK>(pi1, pi2, red, slot);
+            btop2<BLOCK>(pk1, pk2, red, slot);
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int r = t + u * BLOCK;
+                if (r == is || r == k) {
+#pragma unroll
+                    for (int i = 0; i < kBM; ++i) L[u][i] = 0;
+                    L[u][0] = r == is ? pi1 : pk1;
+                    B[u] = r == is ? pi2 : pk2;
+                }
+            }
+            __syncthreads();
+            const int nd = dirty_n;
+            // full re-evaluation of agents whose list ran empty, one per wave
+            for (int e = w; e < nd; e += NW) {
+                const int r = dirty_list[e];
+                u64 b1, b2;
+                wave_eval_row(A, I.AT, n, r, rt, rd, rowbuf[w], b1, b2);
+                if (lane == 0) {
+                    I.lists[2 * r] = b1;
+                    I.lists[2 * r + 1] = b2;
+                }
+            }
+            rescans += nd;
+            __syncthreads();
+            if (nd) {
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) {
+                    const int r = t + u * BLOCK;
+                    if (r < n && r != is && r != k && lmax(L[u]) == 0) {
+                        L[u][0] = I.lists[2 * r];
+                        B[u] = I.lists[2 * r + 1];
+                    }
+                }
+            }
+        }
+
+        // ---- 5. output ---------------------------------------------------------------------------
+        for (int r = t; r < n; r += BLOCK) I.tau[r] = rt[r];
+        if (t == 0) {
+            I.res[0] = f0;
+            I.res[1] = f0 + gsum;
+            I.res[2] = S;
+            I.res[3] = rescans;
+            I.res[4] = DGS_OK;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
+                        int64_t max_switches, int block, int grid, hipStream_t s) {
+    if (block == 512) {
+        hipLaunchKernelGGL(k_batch_solve<512>, dim3((unsigned)grid), dim3(512), 0, s, items, order, count, queue,
+                           max_switches);
+    } else {
+        hipLaunchKernelGGL(k_batch_solve<256>, dim3((unsigned)grid), dim3(256), 0, s, items, order, count, queue,
+                           max_switches);
+    }
+    return hipGetLastError();
+}
+
+int batch_grid_limit(int block) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = block == 512
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<512>, 512, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<256>, 256, 0);
+    if (e != hipSuccess || per < 1) return 0;
+    return cus * per;
+}
+
+}  // namespace dgs

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/dgs.h"
+
 namespace dgs {
 
 typedef unsigned long long u64;
@@ -21,6 +23,9 @@ typedef unsigned long long u64;
 // Per-agent best record: bk = packed key of the best exchange (gain, job),
 // bb = bound key (every other exchange of the agent is <= bb), bc = the
 // partner agent of the best exchange.
+// Length of the candidate lists the full evaluation hands to the switching loop.
+constexpr int kScanListLen = 8;
+
 struct Instance {
     int32_t n = 0;
     const int32_t *A = nullptr;
@@ -39,6 +44,9 @@ struct Instance {
     int32_t *flags = nullptr;    // [0] range error, [1] permutation error, [2] wait timed out
     void *words = nullptr;       // exchange words of the switching loop
     void *replica = nullptr;     // private replicas of the switching loop (large n)
+    void *greedy = nullptr;      // scratch of the greedy start
+    void *scan = nullptr;        // scratch of the difference evaluation (per-block top-2)
+    u64 *lists = nullptr;        // [n][kScanListLen] initial candidate lists (keys, 0 = empty)
 };
 
 size_t loop_record_bytes();
@@ -47,12 +55,19 @@ int loop_grid_size(int device);
 hipError_t launch_range_check(const int32_t *A, int64_t count, int32_t *flag, hipStream_t s);
 hipError_t launch_greedy(const int32_t *A, int32_t n, int32_t *tau, int32_t *sigma,
                          hipStream_t s);
+// Greedy start in rounds (dgs_greedy.hip); scratch of greedy_scratch_bytes(n).
+size_t greedy_scratch_bytes(int n);
+hipError_t launch_greedy_rounds(const int32_t *A, int32_t n, int32_t *tau, int32_t *sigma, void *scratch,
+                                int32_t *err, hipStream_t s);
 hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, int32_t *flag,
                                  hipStream_t s);
 hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t n, hipStream_t s);
 hipError_t launch_build_w(const int32_t *A, const int32_t *tau, int32_t n, int32_t *W, int32_t *d,
                           int64_t *f0, hipStream_t s);
 hipError_t launch_scan_rows(const Instance &I, hipStream_t s);
+// Symmetric tile-pair difference evaluation (dgs_scan.hip).
+size_t scan_pairs_scratch_bytes(int n);
+hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s);
 hipError_t launch_switch_loop(const Instance &I, int64_t max_switches, int grid, hipStream_t s);
 // Switching loop with fence-free exchange (dgs_switch.hip), for 2 <= n <= kSwitchExMaxN.
 constexpr int kSwitchExMaxN = 65535;
@@ -60,8 +75,34 @@ int switch_ex_grid(int n);
 size_t switch_ex_word_bytes(int n);
 bool switch_ex_lds_replica(int n);
 size_t switch_ex_replica_bytes(int n);
+// coop: cooperative launch (co-residency guaranteed by the runtime); else a
+// plain launch whose caller guarantees that its workgroups fit beside the
+// other persistent work on the device.
 hipError_t launch_switch_ex(const Instance &I, int64_t max_switches, void *words, void *replica, int32_t *err,
-                            hipStream_t s);
+                            bool coop, hipStream_t s);
+
+// Internal entry points used by the server (dgs_api.cpp).
+dgs_status solve_internal(const int32_t *benefit, int32_t n, int32_t *assign_out, int64_t max_switches, bool dev,
+                          bool coop, hipStream_t s, dgs_result *res);
+dgs_status solve_batch_internal(int32_t count, const int32_t *const *benefits, const int32_t *ns,
+                                int32_t *const *outs, dgs_result *results, int64_t max_switches, int grid_cap,
+                                hipStream_t s);
+int device_cus();
+
+// Batched single-workgroup solver (dgs_batch.hip) for instances with n <= kBatchMaxN.
+constexpr int kBatchMaxN = 2048;
+struct BatchItem {
+    const int32_t *A;  // n x n benefits (device)
+    int32_t *tau;      // n outputs (device)
+    int32_t *AT;       // n x n scratch
+    u64 *lists;        // 2n scratch
+    int64_t *res;      // [0] f0 [1] f [2] switches [3] re-evaluations [4] status
+    int n;
+    int pad;
+};
+hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
+                        int64_t max_switches, int block, int grid, hipStream_t s);
+int batch_grid_limit(int block);
 
 hipError_t launch_export_best(const Instance &I, int64_t *gain_out, int32_t *job_out,
                               hipStream_t s);

@@ -1,0 +1,212 @@
+// Difference evaluation of every agent (Section 3.2, Algorithm 2) on gfx950,
+// reading every entry of the working matrix once.
+//
+// With W[r][c] = a[r][tau(c)] and d[c] = W[c][c], the 2-exchange of agents
+// i and k gains g(i, k) = W[i][k] + W[k][i] - d[i] - d[k] = g(k, i).  The
+// agents are cut into blocks of kTile; the workgroup of block pair (I, K),
+// I <= K, loads tile W[I][K] and tile W[K][I] once and scores every pair
+// (i in I, k in K) for both agents: for agent i the candidate is
+// (g, job tau(k)), for agent k it is (g, job tau(i)).  Each workgroup writes
+// a top-2 (best, second) per agent and per partner block; k_scan_reduce
+// merges an agent's blocks into its best exchange and the second best
+// (the bound of the candidate list).  Ties: larger gain, then lower job.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dgs_device.h"
+#include "dgs_internal.h"
+
+namespace dgs {
+namespace {
+
+using namespace dev;
+
+constexpr int kTile = 64;
+constexpr int kScanBlock = 256;
+constexpr int kPad = kTile + 1;
+constexpr int kListLen = kScanListLen;
+
+// Triangular index p -> (I, K), I <= K < nb, row-major over I.
+__device__ __forceinline__ void pair_of(long long p, int nb, int &I, int &K) {
+    // pairs before row I: I*nb - I*(I-1)/2
+    const double b = 2.0 * nb + 1.0;
+    int i = (int)((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
+    if (i < 0) i = 0;
+    if (i > nb - 1) i = nb - 1;
+    auto start = [&](int r) { return (long long)r * nb - (long long)r * (r - 1) / 2; };
+    while (i > 0 && start(i) > p) --i;
+    while (i + 1 < nb && start(i + 1) <= p) ++i;
+    I = i;
+    K = i + (int)(p - start(i));
+}
+
+struct ScanParams {
+    const int32_t *W;
+    const int32_t *tau;
+    const int32_t *d;
+    u64 *part;  // [n][nb][2]
+    int n;
+    int nb;
+};
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_pairs(ScanParams P) {
+    __shared__ int32_t tA[kTile][kPad];  // tA[i][k] = W[I*T + i][K*T + k]
+    __shared__ int32_t tB[kTile][kPad];  // tB[k][i] = W[K*T + k][I*T + i]
+    __shared__ int32_t dI[kTile], dK[kTile], jI[kTile], jK[kTile];
+    int I, K;
+    pair_of((long long)blockIdx.x, P.nb, I, K);
+    const int n = P.n;
+    const int i0 = I * kTile, k0 = K * kTile;
+    const int t = threadIdx.x;
+    // load both tiles: 64 rows x 16 int4 each; thread t loads 4 int4 per tile
+    const bool full = (n % 4 == 0) && i0 + kTile <= n && k0 + kTile <= n;
+    if (full) {
+        int4 va[4], vb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = t + u * kScanBlock;  // 0..1023
+            const int r = e >> 4, c4 = (e & 15) * 4;
+            va[u] = *(const int4 *)(P.W + (int64_t)(i0 + r) * n + k0 + c4);
+            vb[u] = *(const int4 *)(P.W + (int64_t)(k0 + r) * n + i0 + c4);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = t + u * kScanBlock;
+            const int r = e >> 4, c4 = (e & 15) * 4;
+            tA[r][c4] = va[u].x;
+            tA[r][c4 + 1] = va[u].y;
+            tA[r][c4 + 2] = va[u].z;
+            tA[r][c4 + 3] = va[u].w;
+            tB[r][c4] = vb[u].x;
+            tB[r][c4 + 1] = vb[u].y;
+            tB[r][c4 + 2] = vb[u].z;
+            tB[r][c4 + 3] = vb[u].w;
+        }
+    } else {
+        for (int e = t; e < kTile * kTile; e += kScanBlock) {
+            const int r = e >> 6, c = e & 63;
+            tA[r][c] = (i0 + r < n && k0 + c < n) ? P.W[(int64_t)(i0 + r) * n + k0 + c] : 0;
+            tB[r][c] = (k0 + r < n && i0 + c < n) ? P.W[(int64_t)(k0 + r) * n + i0 + c] : 0;
+        }
+    }
+    if (t < kTile) {
+        dI[t] = i0 + t < n ? P.d[i0 + t] : 0;
+        jI[t] = i0 + t < n ? P.tau[i0 + t] : 0;
+    } else if (t < 2 * kTile) {
+        const int x = t - kTile;
+        dK[x] = k0 + x < n ? P.d[k0 + x] : 0;
+        jK[x] = k0 + x < n ? P.tau[k0 + x] : 0;
+    }
+    __syncthreads();
+
+    // rows of block I against partners in K: thread t -> row t/4, partners (t%4)*16 ..
+    {
+        const int i = t >> 2, q = t & 3;
+        u64 b1 = 0, b2 = 0;
+        if (i0 + i < n) {
+            const int di = dI[i];
+#pragma unroll 4
+            for (int e = 0; e < 16; ++e) {
+                const int k = q * 16 + e;
+                if (k0 + k >= n || (I == K && k == i)) continue;
+                const int g = (tA[i][k] + tB[k][i]) - (di + dK[k]);
+                top2_push(b1, b2, mk_key(g, jK[k]));
+            }
+        }
+        // merge the 4 quarter-threads of row i (adjacent lanes)
+#pragma unroll
+        for (int m = 1; m <= 2; m <<= 1) top2_merge(b1, b2, shfl_xor64(b1, m), shfl_xor64(b2, m));
+        if (q == 0 && i0 + i < n) {
+            u64 *o = P.part + ((size_t)(i0 + i) * P.nb + K) * 2;
+            o[0] = b1;
+            o[1] = b2;
+        }
+    }
+    if (I == K) return;
+    // rows of block K against partners in I
+    {
+        const int k = t >> 2, q = t & 3;
+        u64 b1 = 0, b2 = 0;
+        if (k0 + k < n) {
+            const int dk = dK[k];
+#pragma unroll 4
+            for (int e = 0; e < 16; ++e) {
+                const int i = q * 16 + e;
+                if (i0 + i >= n) continue;
+                const int g = (tA[i][k] + tB[k][i]) - (dI[i] + dk);
+                top2_push(b1, b2, mk_key(g, jI[i]));
+            }
+        }
+#pragma unroll
+        for (int m = 1; m <= 2; m <<= 1) top2_merge(b1, b2, shfl_xor64(b1, m), shfl_xor64(b2, m));
+        if (q == 0 && k0 + k < n) {
+            u64 *o = P.part + ((size_t)(k0 + k) * P.nb + I) * 2;
+            o[0] = b1;
+            o[1] = b2;
+        }
+    }
+}
+
+// One wave per agent: merge its nb block top-2s into the agent's candidate
+// list.  Every candidate that is not a block's best is <= its block's
+// second, so B = max over blocks of the second is a bound for everything
+// outside the block bests; the list is the kListLen best block bests above
+// B, and the bound is B or the next block best above it.
+__global__ __launch_bounds__(256) void k_scan_reduce(const u64 *__restrict__ part, int n, int nb,
+                                                      const int32_t *__restrict__ sigma, u64 *bk, u64 *bb,
+                                                      int32_t *bc, u64 *lists) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= n) return;
+    const u64 *p = part + (size_t)r * nb * 2;
+    u64 bnd = 0;
+    for (int x = lane; x < nb; x += 64) bnd = umax64(bnd, p[2 * x + 1]);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) bnd = umax64(bnd, shfl_xor64(bnd, m));
+    // up to kListLen + 1 rounds of "largest block best above the bound"
+    u64 taken_max = ~(u64)0;  // keys already emitted are >= this
+    u64 out = 0;              // lane i < kListLen keeps entry i
+    u64 first = 0;
+    for (int round = 0; round <= kListLen; ++round) {
+        u64 m1 = 0;
+        for (int x = lane; x < nb; x += 64) {
+            const u64 k = p[2 * x];
+            if (k > bnd && k < taken_max) m1 = umax64(m1, k);
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) m1 = umax64(m1, shfl_xor64(m1, m));
+        if (m1 == 0) break;
+        if (round == kListLen) {
+            bnd = m1;  // the next block best above B becomes the bound
+            break;
+        }
+        if (round == 0) first = m1;
+        if (lane == round) out = m1;
+        taken_max = m1;
+    }
+    if (lane < kListLen) lists[(size_t)r * kListLen + lane] = out;
+    if (lane == 0) {
+        bk[r] = first;
+        bb[r] = bnd;
+        bc[r] = first ? sigma[key_index(first)] : -1;
+    }
+}
+
+}  // namespace
+
+size_t scan_pairs_scratch_bytes(int n) {
+    const size_t nb = ((size_t)n + kTile - 1) / kTile;
+    return (size_t)n * nb * 2 * sizeof(u64);
+}
+
+hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s) {
+    const int nb = (I.n + kTile - 1) / kTile;
+    const long long pairs = (long long)nb * (nb + 1) / 2;
+    ScanParams P{I.W, I.tau, I.d, (u64 *)scratch, I.n, nb};
+    hipLaunchKernelGGL(k_scan_pairs, dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
+                       nb, I.sigma, I.bk, I.bb, I.bc, I.lists);
+    return hipGetLastError();
+}
+
+}  // namespace dgs

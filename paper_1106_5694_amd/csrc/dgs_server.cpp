@@ -1,9 +1,19 @@
-// dgs_server_*: a request loop for periodic LSAP instances (include/dgs.h).
+// dgs_server_*: a request loop for periodic LSAP instances with continuous
+// batching (include/dgs.h).
 //
-// Requests are admitted against a device-memory budget and a slot count,
-// solved on the device by worker threads (each with its own stream, so the
-// copy of one request overlaps the solve of another), and handed back
-// through tickets.  Results are identical to dgs_solve_ex on the same input.
+// Requests wait in arrival order.  Two kinds of workers take them:
+//   * the small-request worker: every time it is free it takes *all* waiting
+//     requests with n <= kBatchMaxN that fit the device-memory budget and
+//     solves them in one batched launch (one workgroup per instance), so
+//     requests that arrive while a batch runs join the next one;
+//   * large-request workers (one stream each): a waiting large request starts
+//     as soon as its device footprint fits the memory budget and its
+//     switching loop fits the compute units left over by the requests
+//     already running, and its kernels overlap theirs on the device.
+// The switching loops run as plain launches: the server admits them only
+// while the workgroups of all running loops fit the device together, which
+// is what a cooperative launch would otherwise guarantee for a single one.
+// Every result is identical to dgs_solve on the same input.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +27,7 @@
 #include <vector>
 
 #include "../../include/dgs.h"
+#include "dgs_internal.h"
 
 namespace {
 
@@ -37,12 +48,21 @@ struct Done {
     Clock::time_point finished;
 };
 
+constexpr int kLargeWorkers = 4;
+
+// Workgroups the switching loop of an n-agent request keeps resident.
+int loop_wgs(int32_t n) {
+    if (n <= dgs::kBatchMaxN) return 0;
+    return dgs::switch_ex_grid(n);
+}
+
 }  // namespace
 
 struct dgs_server {
     dgs_server_config cfg;
+    int cus = 0;
     std::mutex mu;
-    std::condition_variable cv_work;  // workers wait for requests / memory
+    std::condition_variable cv_work;  // workers wait for requests / capacity
     std::condition_variable cv_done;  // waiters wait for results
     std::deque<Request> queue;
     std::unordered_map<uint64_t, Done> done;
@@ -50,6 +70,8 @@ struct dgs_server {
     uint64_t next_ticket = 1;
     uint64_t bytes_in_use = 0;
     int32_t resident = 0;
+    int wgs_in_use = 0;       // resident switching-loop workgroups of large requests
+    bool small_running = false;
     bool stopping = false;
     std::vector<std::thread> workers;
     std::vector<double> lat_us;
@@ -60,44 +82,127 @@ struct dgs_server {
 
 namespace {
 
-void worker_main(dgs_server *s) {
+void finish(dgs_server *s, const Request &r, Done &&d) {
+    s->lat_us.push_back(std::chrono::duration<double, std::micro>(d.finished - r.submitted).count());
+    s->completed += 1;
+    s->last_finish = d.finished;
+    s->pending_n.erase(r.ticket);
+    s->done.emplace(r.ticket, std::move(d));
+}
+
+void small_worker(dgs_server *s) {
+    hipStream_t stream = nullptr;
+    (void)hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+    for (;;) {
+        std::vector<Request> batch;
+        int grid_cap = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            auto has_small = [&] {
+                for (const Request &r : s->queue)
+                    if (r.n <= dgs::kBatchMaxN) return true;
+                return false;
+            };
+            s->cv_work.wait(lk, [&] { return has_small() || (s->stopping && s->queue.empty()); });
+            if (!has_small()) break;
+            // every waiting small request that fits the budget and the slots joins
+            for (auto it = s->queue.begin(); it != s->queue.end();) {
+                if (it->n <= dgs::kBatchMaxN && s->resident < s->cfg.max_slots &&
+                    s->bytes_in_use + it->bytes <= s->cfg.hbm_budget_bytes) {
+                    s->bytes_in_use += it->bytes;
+                    s->resident += 1;
+                    batch.push_back(*it);
+                    it = s->queue.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            if (batch.empty()) {
+                // capacity is held by running requests: wait for a completion
+                s->cv_work.wait(lk);
+                continue;
+            }
+            s->small_running = true;
+            grid_cap = std::max(1, s->cus - s->wgs_in_use);
+        }
+        std::vector<const int32_t *> bens;
+        std::vector<int32_t> ns;
+        std::vector<Done> outs(batch.size());
+        std::vector<int32_t *> optr;
+        std::vector<dgs_result> res(batch.size());
+        for (size_t i = 0; i < batch.size(); ++i) {
+            bens.push_back(batch[i].benefit);
+            ns.push_back(batch[i].n);
+            outs[i].tau.resize((size_t)batch[i].n);
+            optr.push_back(outs[i].tau.data());
+        }
+        const dgs_status st = dgs::solve_batch_internal((int32_t)batch.size(), bens.data(), ns.data(),
+                                                        optr.data(), res.data(), -1, grid_cap, stream);
+        const auto now = Clock::now();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (size_t i = 0; i < batch.size(); ++i) {
+                outs[i].res = res[i];
+                outs[i].st = st;
+                outs[i].finished = now;
+                s->bytes_in_use -= batch[i].bytes;
+                s->resident -= 1;
+                finish(s, batch[i], std::move(outs[i]));
+            }
+            s->small_running = false;
+        }
+        s->cv_done.notify_all();
+        s->cv_work.notify_all();
+    }
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+void large_worker(dgs_server *s) {
     hipStream_t stream = nullptr;
     (void)hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
     for (;;) {
         Request r;
+        int wgs = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            // FIFO admission: the head waits until its footprint fits.
-            s->cv_work.wait(lk, [&] {
-                if (s->queue.empty()) return s->stopping;
-                const Request &h = s->queue.front();
-                return s->resident < s->cfg.max_slots && s->bytes_in_use + h.bytes <= s->cfg.hbm_budget_bytes;
-            });
-            if (s->queue.empty() && s->stopping) break;
-            r = s->queue.front();
-            s->queue.pop_front();
+            auto pick = [&]() -> std::deque<Request>::iterator {
+                // the oldest large request that fits memory, slots and compute units
+                for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+                    if (it->n <= dgs::kBatchMaxN) continue;
+                    const int need = loop_wgs(it->n);
+                    if (s->resident < s->cfg.max_slots && s->bytes_in_use + it->bytes <= s->cfg.hbm_budget_bytes &&
+                        s->wgs_in_use + need <= s->cus)
+                        return it;
+                    return s->queue.end();  // keep arrival order among large requests
+                }
+                return s->queue.end();
+            };
+            auto has_large = [&] {
+                for (const Request &q : s->queue)
+                    if (q.n > dgs::kBatchMaxN) return true;
+                return false;
+            };
+            s->cv_work.wait(lk, [&] { return pick() != s->queue.end() || (s->stopping && !has_large()); });
+            auto it = pick();
+            if (it == s->queue.end()) break;
+            r = *it;
+            s->queue.erase(it);
+            wgs = loop_wgs(r.n);
             s->bytes_in_use += r.bytes;
             s->resident += 1;
+            s->wgs_in_use += wgs;
         }
         Done d;
         d.tau.resize((size_t)r.n);
-        dgs_options opt;
-        opt.max_switches = -1;
-        opt.init_assign = nullptr;
-        opt.flags = 0;
-        opt.stream = stream;
         std::memset(&d.res, 0, sizeof d.res);
-        d.st = dgs_solve_ex(r.benefit, r.n, d.tau.data(), &opt, &d.res);
+        d.st = dgs::solve_internal(r.benefit, r.n, d.tau.data(), -1, false, /*coop=*/false, stream, &d.res);
         d.finished = Clock::now();
         {
             std::lock_guard<std::mutex> lk(s->mu);
             s->bytes_in_use -= r.bytes;
             s->resident -= 1;
-            s->lat_us.push_back(std::chrono::duration<double, std::micro>(d.finished - r.submitted).count());
-            s->completed += 1;
-            s->last_finish = d.finished;
-            s->pending_n.erase(r.ticket);
-            s->done.emplace(r.ticket, std::move(d));
+            s->wgs_in_use -= wgs;
+            finish(s, r, std::move(d));
         }
         s->cv_done.notify_all();
         s->cv_work.notify_all();
@@ -121,17 +226,22 @@ extern "C" {
 
 uint64_t dgs_server_footprint(int32_t n) {
     const uint64_t nn = (uint64_t)n * (uint64_t)n;
-    return 3 * 4 * nn + 48 * (uint64_t)n + (1u << 20);
+    if (n <= dgs::kBatchMaxN) return 2 * 4 * nn + 32 * (uint64_t)n + 4096;  // copy + transpose
+    return 3 * 4 * nn + 2 * 16 * (uint64_t)n * (((uint64_t)n + 63) / 64) + 256 * (uint64_t)n + (1u << 20);
 }
 
 dgs_status dgs_server_create(const dgs_server_config *cfg, dgs_server **out) {
     if (!out) return DGS_E_INVAL;
+    const int cus = dgs::device_cus();
+    if (cus < 1) return DGS_E_DEVICE;
     dgs_server *s = new dgs_server();
+    s->cus = cus;
     s->cfg.hbm_budget_bytes = (cfg && cfg->hbm_budget_bytes) ? cfg->hbm_budget_bytes : (64ull << 30);
     s->cfg.max_slots = (cfg && cfg->max_slots > 0) ? cfg->max_slots : 64;
     s->cfg.max_n = (cfg && cfg->max_n > 0) ? cfg->max_n : 16384;
-    const int nworkers = std::max(1, std::min(4, (int)s->cfg.max_slots));
-    for (int i = 0; i < nworkers; ++i) s->workers.emplace_back(worker_main, s);
+    if (s->cfg.max_n > dgs::kSwitchExMaxN) s->cfg.max_n = dgs::kSwitchExMaxN;
+    s->workers.emplace_back(small_worker, s);
+    for (int i = 0; i < kLargeWorkers; ++i) s->workers.emplace_back(large_worker, s);
     *out = s;
     return DGS_OK;
 }
@@ -141,6 +251,7 @@ dgs_status dgs_server_submit(dgs_server *s, const int32_t *benefit, int32_t n, u
     if (n < 1 || n > s->cfg.max_n) return DGS_E_INVAL;
     const uint64_t bytes = dgs_server_footprint(n);
     if (bytes > s->cfg.hbm_budget_bytes) return DGS_E_NOMEM;
+    if (loop_wgs(n) > s->cus) return DGS_E_NOMEM;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) return DGS_E_INVAL;
@@ -159,7 +270,7 @@ dgs_status dgs_server_submit(dgs_server *s, const int32_t *benefit, int32_t n, u
         s->queue.push_back(r);
         *ticket_out = r.ticket;
     }
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();
     return DGS_OK;
 }
 

@@ -73,8 +73,8 @@ struct ExParams {
     int32_t *tau;          // in: start assignment; out: final assignment
     const int32_t *sigma;  // start inverse assignment
     const int32_t *d;      // start benefits d[c] = a[c][tau(c)]
-    const u64 *bk;         // full-scan best keys (long form)
-    const u64 *bb;         // full-scan second keys (long form): initial bounds
+    const u64 *lists;      // full-evaluation candidate lists [n][kScanListLen] (long form)
+    const u64 *bb;         // full-evaluation bounds (long form)
     u64 *words;            // 2 * G * kWords exchange words
     unsigned char *rep;    // private replicas (global mode): G * n * 8 bytes
     int64_t *stats;        // [0] switches [1] gain sum [3] re-evaluations [4] stalled rounds
@@ -285,7 +285,8 @@ __global__ __launch_bounds__(kT) void k_switch_ex(ExParams P) {
     for (int i = 0; i < kM; ++i) L[i] = 0;
     u64 B = 0;
     if (mine) {
-        L[0] = from_long(P.bk[r]);
+#pragma unroll
+        for (int i = 0; i < kM && i < kScanListLen; ++i) L[i] = from_long(P.lists[(size_t)r * kScanListLen + i]);
         B = from_long(P.bb[r]);
     }
     bool dirty = false;
@@ -636,7 +637,7 @@ size_t switch_ex_replica_bytes(int n) {
 }
 
 hipError_t launch_switch_ex(const Instance &I, int64_t max_switches, void *words, void *replica,
-                            int32_t *err, hipStream_t s) {
+                            int32_t *err, bool coop, hipStream_t s) {
     ExParams P;
     P.A = I.A;
     P.AT = I.AT;
@@ -644,7 +645,7 @@ hipError_t launch_switch_ex(const Instance &I, int64_t max_switches, void *words
     P.tau = I.tau;
     P.sigma = I.sigma;
     P.d = I.d;
-    P.bk = I.bk;
+    P.lists = I.lists;
     P.bb = I.bb;
     P.words = (u64 *)words;
     P.rep = (unsigned char *)replica;
@@ -662,12 +663,20 @@ hipError_t launch_switch_ex(const Instance &I, int64_t max_switches, void *words
         hipError_t e = hipFuncSetAttribute((const void *)k_switch_ex<true>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
+        if (!coop) {
+            hipLaunchKernelGGL(k_switch_ex<true>, dim3((unsigned)grid), dim3(kT), shm, s, P);
+            return hipGetLastError();
+        }
         return hipLaunchCooperativeKernel((const void *)k_switch_ex<true>, dim3((unsigned)grid), dim3(kT), args,
                                           (unsigned)shm, s);
     }
     hipError_t e = hipFuncSetAttribute((const void *)k_switch_ex<false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)wl_bytes);
     if (e != hipSuccess) return e;
+    if (!coop) {
+        hipLaunchKernelGGL(k_switch_ex<false>, dim3((unsigned)grid), dim3(kT), wl_bytes, s, P);
+        return hipGetLastError();
+    }
     return hipLaunchCooperativeKernel((const void *)k_switch_ex<false>, dim3((unsigned)grid), dim3(kT), args,
                                       (unsigned)wl_bytes, s);
 }

@@ -195,15 +195,74 @@ def test_batched_equals_solo(dgs):
 
 
 def test_server_equals_solo(dgs):
-    ns = [128, 300, 64, 1000, 257]
+    # small requests (batched launches) and large ones (concurrent switching
+    # loops on worker streams) in one mix: each result equals the same
+    # instance solved alone, and the oracle
+    ns = [128, 2500, 300, 64, 3000, 1000, 257, 2049, 5, 2300]
     As = [gen.lowrank_matrix(n, 60 + i) for i, n in enumerate(ns)]
-    say("case server")
-    with dgs.Server(max_slots=3) as srv:
+    say(f"case server mix: {ns}")
+    with dgs.Server(max_slots=6) as srv:
         tickets = [srv.submit(A) for A in As]
-        outs = [srv.wait(t, timeout_us=60_000_000) for t in tickets]
+        outs = [srv.wait(t, timeout_us=120_000_000) for t in tickets]
         st = srv.stats()
     for A, out in zip(As, outs):
         assert out is not None
+        alone, res_alone = dgs.solve(A)
+        assert (out[0] == alone).all() and out[1]["total_benefit"] == res_alone["total_benefit"]
+        assert out[1]["switches"] == res_alone["switches"]
         ref = oracle.dgs_incr(A)
         assert (out[0] == ref["tau"]).all() and out[1]["total_benefit"] == ref["f"]
-    assert st["completed"] == len(As)
+    assert st["completed"] == len(As) and st["queued"] == 0
+    assert 0 < st["p50_us"] <= st["p99_us"]
+
+
+def test_server_budget_admission(dgs):
+    # a budget that holds one large request at a time still completes every
+    # request; a request that can never fit is refused at submit
+    n = 2200
+    budget = dgs.server_footprint(n) + dgs.server_footprint(512)
+    As = [gen.uniform_matrix(n, 0, 1000, 80 + i) for i in range(3)] + [gen.uniform_matrix(512, 0, 1000, 90)]
+    with dgs.Server(hbm_budget_bytes=budget) as srv:
+        tickets = [srv.submit(A) for A in As]
+        outs = [srv.wait(t, timeout_us=120_000_000) for t in tickets]
+        with pytest.raises(dgs.DGSError) as e:
+            srv.submit(gen.uniform_matrix(3000, 0, 10, 1))
+        assert e.value.status == dgs.DGS_E_NOMEM
+    for A, out in zip(As, outs):
+        ref = oracle.dgs_incr(A)
+        assert (out[0] == ref["tau"]).all() and out[1]["switches"] == ref["S"]
+
+
+def test_batched_workload_sample(dgs):
+    # the batched workload's shape: log-uniform n in [64, 2048], benefits in [0, 10000);
+    # every instance of a mixed batch equals the oracle, and one instance above the
+    # single-workgroup limit takes the single-instance path inside the same call
+    ns = list(gen.loguniform_sizes(48, 64, 2048, 7)) + [2048, 2049, 3000]
+    As = [gen.uniform_matrix(int(n), 0, 10000, 900 + i) for i, n in enumerate(ns)]
+    say(f"case batched sample: {len(As)} instances, max n {max(ns)}")
+    taus, results = dgs.solve_batched(As)
+    for A, tau, res in zip(As, taus, results):
+        ref = oracle.dgs_incr(A)
+        assert (tau == ref["tau"]).all()
+        assert res["total_benefit"] == ref["f"] and res["switches"] == ref["S"]
+        assert res["initial_benefit"] == oracle.objective(A, oracle.greedy(A))
+
+
+def test_batched_device_pointers_and_prefix(dgs):
+    import torch
+    ns = [5, 130, 700, 1500]
+    As = [gen.lowrank_matrix(n, 70 + i) for i, n in enumerate(ns)]
+    Ads = [torch.from_numpy(A).cuda() for A in As]
+    taus, results = dgs.solve_batched(Ads, max_switches=3)
+    torch.cuda.synchronize()
+    for A, tau, res in zip(As, taus, results):
+        ref = oracle.dgs_incr(A, max_switches=3)
+        assert (tau.cpu().numpy() == ref["tau"]).all() and res["switches"] == ref["S"]
+
+
+def test_batched_out_of_range(dgs):
+    As = [gen.uniform_matrix(100, 0, 10, 1), gen.uniform_matrix(50, 0, 10, 2)]
+    As[1][3, 4] = -(1 << 29)
+    with pytest.raises(dgs.DGSError) as e:
+        dgs.solve_batched(As)
+    assert e.value.status == dgs.DGS_E_RANGE
