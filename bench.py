@@ -91,6 +91,9 @@ def main() -> int:
     ap.add_argument("--workload", default="lowrank16384", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 launches): the reference "
+                         "kernel that scales the HBM byte counters of a profile")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the method runs each instance on a "
@@ -106,6 +109,15 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}))
+        return 0
     dgs.lib()
     spec = WORKLOADS[args.workload]
     n = spec["n"]
@@ -184,4 +196,9 @@ def main() -> int:
 
 
 if __name__ == "__main__":
-    sys.exit(main())
+    # success returns normally instead of raising SystemExit: under
+    # rocprofv3 the SystemExit path ends the process before the profiler
+    # has written its database
+    rc = main()
+    if rc:
+        sys.exit(rc)
