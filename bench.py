@@ -1,19 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark: Deep Greedy Switching on one MI355X.
 
-One step = one full DGS solve (greedy start, layout, difference
+Default: one step = one full DGS solve (greedy start, layout, difference
 evaluation of every agent, switching until no improving 2-exchange is
 left) of the n = 16384 low-rank-plus-noise instance, with the benefit
-matrix already resident in HBM.  Prints one JSON line.
+matrix already resident in HBM.  Prints one JSON line; the line also
+carries a short measurement of the batched workload (512 instances in one
+graph-captured launch, against a loop of single-instance solves).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Other workloads: lowrank4096, uniform256 (single instances), batched512
+(the batched workload as the step) and serving (Poisson arrivals at
+200/s for --serve-seconds, continuous batching against a plain
+one-request-at-a-time loop).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -23,11 +32,18 @@ if ROOT not in sys.path:
 METRIC = "LSAP instances/sec and n=16384 solve ms (HBM % of peak); serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
-WORKLOADS = {
+SINGLE = {
     "lowrank16384": dict(n=16384, generator="round((1000*u_i)*c_j)+noise, u,c~U(0.1,1), noise~U{0..99}"),
     "lowrank4096": dict(n=4096, generator="round((1000*u_i)*c_j)+noise, u,c~U(0.1,1), noise~U{0..99}"),
     "uniform256": dict(n=256, generator="iid uniform int32 in [0,1000)"),
 }
+WORKLOADS = sorted(SINGLE) + ["batched512", "serving"]
+
+KERNELS = {"range": "k_range_check", "init": "k_greedy_topk+k_greedy_resolve",
+           "layout": "k_transpose+k_build_w", "scan": "k_scan_pairs+k_scan_reduce",
+           "switch": "k_switch_ex"}
+KERNEL_SOURCES = {"k_switch_ex": "dgs_switch.hip", "k_scan_pairs+k_scan_reduce": "dgs_scan.hip",
+                  "k_batch_solve": "dgs_batch.hip"}
 
 
 def algorithmic_bytes(phase: str, n: int, switches: int, rescans: int) -> int:
@@ -46,6 +62,29 @@ def algorithmic_bytes(phase: str, n: int, switches: int, rescans: int) -> int:
         # each (16n B); per full re-evaluation of one agent: two rows (8n B)
         return 16 * n * switches + 8 * n * rescans
     raise KeyError(phase)
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel and workload, scaled by the copy-kernel calibration; None
+    when there is none or the kernel's source changed since it was taken."""
+    src = KERNEL_SOURCES.get(kernel)
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_counters.txt")
+    if src is None or not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                fields[k.strip()] = v.strip()
+    with open(os.path.join(ROOT, "paper_1106_5694_amd", "csrc", src), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != fields.get("source_sha256"):
+            return None
+    try:
+        return int(float(fields["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(A, switches: int, budget_s: float = 12.0) -> dict:
@@ -83,14 +122,229 @@ def cpu_baseline(A, switches: int, budget_s: float = 12.0) -> dict:
     }
 
 
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def base_line(args, value: float, unit: str, ms_per_step: float, config: dict) -> dict:
+    return {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": unit,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": config,
+    }
+
+
+def run_single(args, dgs, torch, gen, np) -> dict:
+    spec = SINGLE[args.workload]
+    n = spec["n"]
+    t0 = time.perf_counter()
+    A = gen.single_instance(args.workload, args.seed)
+    log(f"generated {args.workload} seed {args.seed} in {time.perf_counter() - t0:.1f} s")
+    Ad = torch.from_numpy(A).to(torch.device("cuda:0"))
+    torch.cuda.synchronize()
+    for w in range(args.warmup):
+        _, res = dgs.solve(Ad, profile=True)
+        log(f"warmup {w}: {res['device_ms']:.2f} ms device, S={res['switches']}")
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tau, res = dgs.solve(Ad, profile=True)
+        results.append(res)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    S = results[-1]["switches"]
+    rescans = results[-1]["rescans"]
+    phases = {}
+    for p in dgs.PHASES:
+        ms = float(np.mean([r["phase_ms"][p] for r in results]))
+        byts = algorithmic_bytes(p, n, S, rescans)
+        gbs = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        phases[p] = {"ms": round(ms, 4), "algorithmic_bytes": byts, "GB/s": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    dominant = max(phases, key=lambda p: phases[p]["ms"])
+    d = phases[dominant]
+    kernel = KERNELS[dominant]
+    roofline = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["hbm_frac"], "traffic": measured_traffic(kernel, args.workload),
+                "kernel": kernel, "phase": dominant, "algorithmic_bytes_per_launch": d["algorithmic_bytes"],
+                "avg_launch_ms": d["ms"]}
+    config = {"workload": args.workload, "n": n, "seed": args.seed, "generator": spec["generator"],
+              "start": "greedy", "switches": S, "rescans": rescans,
+              "initial_benefit": results[-1]["initial_benefit"], "total_benefit": results[-1]["total_benefit"],
+              "device_ms": round(float(np.mean([r["device_ms"] for r in results])), 3)}
+    line = base_line(args, args.steps / wall, "instances/s", 1000.0 * wall / args.steps, config)
+    line["roofline"] = roofline
+    line["phases"] = phases
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(A, S)
+    del Ad, tau
+    torch.cuda.synchronize()
+    return line
+
+
+def run_batched(args, dgs, torch, gen, np, steps: int, warmup: int, count: int = 512) -> dict:
+    """The batched workload: `count` instances, n log-uniform in [64, 2048],
+    iid uniform benefits in [0, 10000), solved by one graph-captured
+    persistent launch per step; against a loop of single-instance solves of
+    the same device-resident instances."""
+    t0 = time.perf_counter()
+    ns = [int(n) for n in gen.loguniform_sizes(count, 64, 2048, args.seed)]
+    As = gen.batch_instances(count, 64, 2048, args.seed)
+    log(f"generated {count} batched instances in {time.perf_counter() - t0:.1f} s")
+    plan = dgs.BatchPlan(ns, autotune=True)
+    _, first = plan.run(As, outs=False)  # upload, tune, capture
+    for _ in range(warmup):
+        plan.run(None, outs=False)
+    t0 = time.perf_counter()
+    ms = []
+    for _ in range(steps):
+        _, res = plan.run(None, outs=False)
+        ms.append(res[0]["device_ms"])
+    wall = time.perf_counter() - t0
+    block, grid = plan.config()
+    plan.close()
+
+    # the plain per-instance solver on the same GPU, inputs resident in HBM
+    Ads = [torch.from_numpy(A).to("cuda:0") for A in As]
+    torch.cuda.synchronize()
+    for A in Ads[:8]:
+        dgs.solve(A)
+    t1 = time.perf_counter()
+    single = [dgs.solve(A)[1] for A in Ads]
+    torch.cuda.synchronize()
+    wall1 = time.perf_counter() - t1
+    same = all(a["total_benefit"] == b["total_benefit"] and a["switches"] == b["switches"]
+               for a, b in zip(first, single))
+    del Ads
+    torch.cuda.synchronize()
+    entries = sum(n * n for n in ns)
+    launch_ms = float(np.mean(ms))
+    gbs = 4 * entries / (launch_ms * 1e-3) / 1e9
+    return {
+        "instances": count, "n_range": [64, 2048], "sum_n2": entries,
+        "instances_per_s": round(count * steps / wall, 2),
+        "ms_per_batch": round(1000.0 * wall / steps, 3),
+        "per_instance_solver": {"instances_per_s": round(count / wall1, 2),
+                                "ms_per_batch": round(1000.0 * wall1, 3)},
+        "speedup_vs_per_instance": round((count * steps / wall) / (count / wall1), 2),
+        "results_identical": bool(same),
+        "autotuned": {"block": block, "grid": grid},
+        "roofline": {"bound": "hbm", "kernel": "k_batch_solve", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes_per_launch": 4 * entries,
+                     "bytes_basis": "every benefit matrix read once", "avg_launch_ms": round(launch_ms, 3),
+                     "traffic": measured_traffic("k_batch_solve", "batched512")},
+    }
+
+
+def run_serving(args, dgs, gen, np) -> dict:
+    """Poisson arrivals at 200/s for --serve-seconds, n log-uniform in
+    [128, 16384], low-rank-plus-noise benefits; the continuous-batching
+    server against a plain loop that solves one request at a time in
+    arrival order, on the same arrival trace."""
+    arrivals, pool_ns = gen.serving_trace(args.serve_seconds, 200.0, 128, 16384, args.seed, 64)
+    t0 = time.perf_counter()
+    pool = [gen.lowrank_matrix(int(n), args.seed * 1_000_003 + p) for p, n in enumerate(pool_ns)]
+    log(f"generated the request pool ({len(pool)} instances) in {time.perf_counter() - t0:.1f} s; "
+        f"{len(arrivals)} requests over {args.serve_seconds} s")
+    reqs = [(float(t), k % len(pool)) for k, t in enumerate(arrivals)]
+
+    # warm the library's workspaces for the larger sizes
+    for p in sorted(range(len(pool)), key=lambda p: -int(pool_ns[p]))[:2]:
+        dgs.solve(pool[p])
+
+    # continuous batching
+    log("serving: continuous batching")
+    with dgs.Server() as srv:
+        start = time.perf_counter()
+        tickets = []
+        for t, p in reqs:
+            now = time.perf_counter() - start
+            if t > now:
+                time.sleep(t - now)
+            tickets.append(srv.submit(pool[p]))
+        for k, tk in enumerate(tickets):
+            assert srv.wait(tk) is not None
+            if (k + 1) % 200 == 0:
+                log(f"serving: {k + 1} of {len(tickets)} requests done")
+        st = srv.stats()
+    cb = {"requests": int(st["completed"]), "instances_per_s": round(st["inst_per_s"], 2),
+          "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1)}
+    log(f"serving: continuous batching done: {cb}")
+
+    # plain: one request at a time, in arrival order
+    log("serving: plain one-at-a-time loop")
+    lat = []
+    queue = []
+    cv = threading.Condition()
+    finished = []
+
+    def worker():
+        while True:
+            with cv:
+                while not queue:
+                    cv.wait()
+                item = queue.pop(0)
+            if item is None:
+                return
+            t_arr, p = item
+            dgs.solve(pool[p])
+            finished.append(time.perf_counter())
+            lat.append(finished[-1] - t_arr)
+            if len(lat) % 200 == 0:
+                log(f"serving: plain loop, {len(lat)} requests done")
+
+    th = threading.Thread(target=worker)
+    th.start()
+    start = time.perf_counter()
+    first_arrival = None
+    for t, p in reqs:
+        now = time.perf_counter() - start
+        if t > now:
+            time.sleep(t - now)
+        with cv:
+            t_arr = time.perf_counter()
+            if first_arrival is None:
+                first_arrival = t_arr
+            queue.append((t_arr, p))
+            cv.notify()
+    with cv:
+        queue.append(None)
+        cv.notify()
+    th.join()
+    lat_us = np.asarray(lat) * 1e6
+    plain = {"requests": len(lat), "instances_per_s": round(len(lat) / max(finished[-1] - first_arrival, 1e-9), 2),
+             "p50_us": round(float(np.percentile(lat_us, 50)), 1),
+             "p99_us": round(float(np.percentile(lat_us, 99)), 1)}
+    log(f"serving: plain done: {plain}")
+    return {"arrival_rate_per_s": 200, "seconds": args.serve_seconds, "n_range": [128, 16384],
+            "pool": len(pool), "continuous_batching": cb, "plain_per_request": plain}
+
+
 def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lowrank16384", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="lowrank16384", choices=WORKLOADS)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="single-instance workloads: skip the batched summary")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches): the reference "
                          "kernel that scales the HBM byte counters of a profile")
@@ -119,78 +373,28 @@ def main() -> int:
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}))
         return 0
     dgs.lib()
-    spec = WORKLOADS[args.workload]
-    n = spec["n"]
-    t0 = time.perf_counter()
-    A = gen.single_instance(args.workload, args.seed)
-    print(f"[bench] generated {args.workload} seed {args.seed} in {time.perf_counter() - t0:.1f} s",
-          file=sys.stderr, flush=True)
-    dev = torch.device("cuda:0")
-    Ad = torch.from_numpy(A).to(dev)
-    torch.cuda.synchronize()
 
-    for w in range(args.warmup):
-        _, res = dgs.solve(Ad, profile=True)
-        print(f"[bench] warmup {w}: {res['device_ms']:.2f} ms device, S={res['switches']}",
-              file=sys.stderr, flush=True)
-
-    results = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        tau, res = dgs.solve(Ad, profile=True)
-        results.append(res)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1000.0 * wall / args.steps
-    value = args.steps / wall
-
-    S = results[-1]["switches"]
-    rescans = results[-1]["rescans"]
-    phases = {}
-    for p in dgs.PHASES:
-        ms = float(np.mean([r["phase_ms"][p] for r in results]))
-        byts = algorithmic_bytes(p, n, S, rescans)
-        gbs = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        phases[p] = {"ms": round(ms, 4), "algorithmic_bytes": byts, "GB/s": round(gbs, 1),
-                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-    dominant = max(phases, key=lambda p: phases[p]["ms"])
-    kernel_names = {"range": "k_range_check", "init": "k_greedy_topk+k_greedy_resolve",
-                    "layout": "k_transpose+k_build_w", "scan": "k_scan_pairs+k_scan_reduce",
-                    "switch": "k_switch_ex"}
-    d = phases[dominant]
-    roofline = {"bound": "hbm", "achieved": d["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["hbm_frac"], "traffic": None, "kernel": kernel_names[dominant],
-                "phase": dominant, "algorithmic_bytes_per_launch": d["algorithmic_bytes"],
-                "avg_launch_ms": d["ms"]}
-
-    line = {
-        "metric": METRIC,
-        "value": round(value, 4),
-        "unit": "instances/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "seed": args.seed, "generator": spec["generator"],
-                   "start": "greedy", "switches": S, "rescans": rescans,
-                   "initial_benefit": results[-1]["initial_benefit"],
-                   "total_benefit": results[-1]["total_benefit"],
-                   "device_ms": round(float(np.mean([r["device_ms"] for r in results])), 3)},
-        "roofline": roofline,
-        "phases": phases,
-    }
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(A, S)
+    if args.workload in SINGLE:
+        line = run_single(args, dgs, torch, gen, np)
+        if not args.no_batched:
+            log("batched workload summary")
+            line["batched"] = run_batched(args, dgs, torch, gen, np, steps=3, warmup=1)
+    elif args.workload == "batched512":
+        b = run_batched(args, dgs, torch, gen, np, steps=args.steps, warmup=args.warmup)
+        config = {"workload": "batched512", "instances": 512, "n": "log-uniform [64, 2048]",
+                  "generator": "iid uniform int32 in [0,10000)", "seed": args.seed}
+        line = base_line(args, b["instances_per_s"], "instances/s", b["ms_per_batch"], config)
+        line["roofline"] = b.pop("roofline")
+        line["batched"] = b
+    else:
+        s = run_serving(args, dgs, gen, np)
+        config = {"workload": "serving", "arrivals": "Poisson 200/s", "seconds": args.serve_seconds,
+                  "n": "log-uniform [128, 16384]", "generator": "low-rank + noise", "seed": args.seed}
+        cb = s["continuous_batching"]
+        line = base_line(args, cb["instances_per_s"], "instances/s",
+                         1000.0 / max(cb["instances_per_s"], 1e-9), config)
+        line["serving"] = s
     print(json.dumps(line), flush=True)
-    del Ad, tau
-    torch.cuda.synchronize()
     dgs.release_cached()
     return 0
 

@@ -59,6 +59,7 @@ typedef enum dgs_status {
 /* dgs_options.flags */
 #define DGS_DEVICE_PTRS 0x1u /* benefit, assign_out, init_assign are device pointers */
 #define DGS_PROFILE 0x2u     /* also time each phase with HIP events (dgs_result.phase_ms) */
+#define DGS_AUTOTUNE 0x4u    /* batch plans: pick the solver's workgroup size by timing it */
 
 /* dgs_result.phase_ms indices (filled only with DGS_PROFILE) */
 #define DGS_PHASE_RANGE 0  /* value-range check of the benefit matrix */
@@ -112,6 +113,47 @@ dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out,
 dgs_status dgs_solve_batched(int32_t count, const int32_t *const *benefits, const int32_t *ns,
                              int32_t *const *assign_outs, dgs_result *results,
                              const dgs_options *opt);
+
+/* ---- Batch plans: the same batch shape solved again and again ----------
+ * A plan fixes `count` instance sizes ns[b] (1 <= n <= 2048 each) and owns
+ * device buffers for every instance's benefit matrix and assignment.  A run
+ * solves all instances (each result identical to dgs_solve_ex on that
+ * instance alone) with one persistent launch, one workgroup per instance,
+ * largest first.  The device work of a run (queue reset, the launch, the
+ * readback of the per-instance results) is captured once in a HIP graph and
+ * replayed by later runs.
+ * Tuning: with DGS_AUTOTUNE in opt->flags, the first run times each
+ * workgroup size of the batched solver (256 or 512 threads, i.e. 8 or 4
+ * agents per thread) on the plan's inputs and keeps the fastest; results do
+ * not depend on the choice.  The choice is kept per size class for the
+ * process, and in the text file named by the environment variable
+ * DGS_TUNE_CACHE when it is set (read by the first plan creation that sees
+ * the variable name that file, its entries overriding earlier choices;
+ * appended after every new tuning).  opt may be NULL; only max_switches and flags are
+ * used (DGS_DEVICE_PTRS is ignored: the plan's buffers are device memory). */
+typedef struct dgs_batch_plan dgs_batch_plan;
+
+dgs_status dgs_batch_plan_create(int32_t count, const int32_t *ns, const dgs_options *opt,
+                                 dgs_batch_plan **out);
+
+/* Device address of instance b's benefit buffer (n*n int32, row-major) and
+ * of its assignment (n int32), valid until the plan is destroyed; NULL for
+ * a bad plan or index. */
+int32_t *dgs_batch_plan_benefit(dgs_batch_plan *p, int32_t b);
+int32_t *dgs_batch_plan_assign(dgs_batch_plan *p, int32_t b);
+
+/* One run.  benefits: NULL (the matrices already sit in the plan's device
+ * buffers) or `count` host pointers copied in first.  assign_outs: NULL
+ * (assignments stay in the plan's device buffers) or `count` host pointers.
+ * results: NULL or `count` records; device_ms is the time of the graph.
+ * Runs of one plan must not overlap (the plan is not thread-safe). */
+dgs_status dgs_batch_plan_run(dgs_batch_plan *p, const int32_t *const *benefits,
+                              int32_t *const *assign_outs, dgs_result *results);
+
+/* Workgroup size and grid the plan launches with (after tuning, if any). */
+dgs_status dgs_batch_plan_config(dgs_batch_plan *p, int32_t *block, int32_t *grid);
+
+void dgs_batch_plan_destroy(dgs_batch_plan *p);
 
 /* Difference evaluation (Section 3.2, Algorithm 2) of every agent for a
  * given assignment: for each agent i, the best 2-exchange gain over all

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(HERE, "libdgs.so")
 DGS_OK, DGS_E_INVAL, DGS_E_RANGE, DGS_E_NOMEM, DGS_E_DEVICE, DGS_E_AGAIN = range(6)
 DGS_DEVICE_PTRS = 0x1
 DGS_PROFILE = 0x2
+DGS_AUTOTUNE = 0x4
 PHASES = ("range", "init", "layout", "scan", "switch")
 MAX_ABS_BENEFIT = (1 << 29) - 1
 
@@ -34,6 +35,8 @@ EXPORTS = (
     "dgs_server_footprint", "dgs_server_create", "dgs_server_submit", "dgs_server_poll",
     "dgs_server_wait", "dgs_server_stats_get", "dgs_server_destroy",
     "dgs_status_string", "dgs_last_error", "dgs_version", "dgs_release_cached",
+    "dgs_batch_plan_create", "dgs_batch_plan_benefit", "dgs_batch_plan_assign", "dgs_batch_plan_run",
+    "dgs_batch_plan_config", "dgs_batch_plan_destroy",
 )
 
 
@@ -104,13 +107,23 @@ def lib() -> ctypes.CDLL:
     L.dgs_server_stats_get.argtypes = [P, ctypes.POINTER(ServerStats)]
     L.dgs_server_destroy.argtypes = [P]
     L.dgs_server_destroy.restype = None
+    L.dgs_batch_plan_create.argtypes = [i32, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
+    L.dgs_batch_plan_benefit.argtypes = [P, i32]
+    L.dgs_batch_plan_benefit.restype = P
+    L.dgs_batch_plan_assign.argtypes = [P, i32]
+    L.dgs_batch_plan_assign.restype = P
+    L.dgs_batch_plan_run.argtypes = [P, P, P, P]
+    L.dgs_batch_plan_config.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.dgs_batch_plan_destroy.argtypes = [P]
+    L.dgs_batch_plan_destroy.restype = None
     L.dgs_status_string.argtypes = [ctypes.c_int]
     L.dgs_status_string.restype = ctypes.c_char_p
     L.dgs_last_error.restype = ctypes.c_char_p
     L.dgs_version.restype = ctypes.c_char_p
     L.dgs_release_cached.restype = None
     for name in ("dgs_solve", "dgs_solve_ex", "dgs_solve_batched", "dgs_diff_eval", "dgs_server_create",
-                 "dgs_server_submit", "dgs_server_poll", "dgs_server_wait", "dgs_server_stats_get"):
+                 "dgs_server_submit", "dgs_server_poll", "dgs_server_wait", "dgs_server_stats_get",
+                 "dgs_batch_plan_create", "dgs_batch_plan_run", "dgs_batch_plan_config"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -239,6 +252,69 @@ def solve_batched(As: Sequence, max_switches: int = -1):
     st = L.dgs_solve_batched(count, bptr, ns.ctypes.data, optr, results, ctypes.byref(opt))
     _check(st, "dgs_solve_batched")
     return outs, [r.as_dict() for r in results]
+
+
+class BatchPlan:
+    """A fixed batch shape (sizes ns, each <= 2048) solved again and again.
+
+    The plan owns the device buffers; run() replays one captured graph.
+    autotune=True times both workgroup sizes of the batched solver on the
+    first run and keeps the faster one.
+    """
+
+    def __init__(self, ns, max_switches: int = -1, autotune: bool = False):
+        L = lib()
+        self.ns = [int(n) for n in ns]
+        arr = np.array(self.ns, dtype=np.int32)
+        opt = Options(max_switches=int(max_switches), init_assign=None,
+                      flags=DGS_AUTOTUNE if autotune else 0, stream=None)
+        h = ctypes.c_void_p()
+        _check(L.dgs_batch_plan_create(len(self.ns), arr.ctypes.data, ctypes.byref(opt), ctypes.byref(h)),
+               "dgs_batch_plan_create")
+        self._h = h
+
+    def run(self, As=None, outs: bool = True):
+        """Solve; As (host matrices) are copied in first when given.
+
+        Returns (taus or None, results).
+        """
+        L = lib()
+        count = len(self.ns)
+        bptr = None
+        if As is not None:
+            hs = [_host_i32(A, (n, n)) for A, n in zip(As, self.ns)]
+            bptr = (ctypes.c_void_p * count)(*[h.ctypes.data for h in hs])
+        taus = None
+        optr = None
+        if outs:
+            taus = [np.empty(n, dtype=np.int32) for n in self.ns]
+            optr = (ctypes.c_void_p * count)(*[t.ctypes.data for t in taus])
+        results = (Result * count)()
+        _check(L.dgs_batch_plan_run(self._h, bptr, optr, results), "dgs_batch_plan_run")
+        return taus, [r.as_dict() for r in results]
+
+    def config(self):
+        b = ctypes.c_int32()
+        g = ctypes.c_int32()
+        _check(lib().dgs_batch_plan_config(self._h, ctypes.byref(b), ctypes.byref(g)), "dgs_batch_plan_config")
+        return int(b.value), int(g.value)
+
+    def close(self):
+        if self._h:
+            lib().dgs_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def release_cached() -> None:

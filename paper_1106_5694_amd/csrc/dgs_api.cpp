@@ -25,7 +25,6 @@
 #include "dgs_internal.h"
 
 namespace dgs {
-namespace {
 
 thread_local std::string g_last_error;
 
@@ -37,15 +36,6 @@ void set_error(const char *fmt, ...) {
     va_end(ap);
     g_last_error = buf;
 }
-
-#define DGS_HIP(call)                                                                       \
-    do {                                                                                    \
-        hipError_t e_ = (call);                                                             \
-        if (e_ != hipSuccess) {                                                             \
-            set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
-            return DGS_E_DEVICE;                                                            \
-        }                                                                                   \
-    } while (0)
 
 // ---- device context ---------------------------------------------------------------
 
@@ -86,6 +76,8 @@ dgs_status ensure_context() {
     if (g_ctx.init_status != DGS_OK) set_error("%s", g_ctx.init_error.c_str());
     return g_ctx.init_status;
 }
+
+namespace {
 
 // ---- workspaces -----------------------------------------------------------------------
 // One workspace holds the device buffers of one instance of size <= cap.

@@ -49,6 +49,20 @@ struct Instance {
     u64 *lists = nullptr;        // [n][kScanListLen] initial candidate lists (keys, 0 = empty)
 };
 
+// Host-side helpers of the C ABI (dgs_api.cpp).
+void set_error(const char *fmt, ...);  // thread-local message for dgs_last_error
+dgs_status ensure_context();            // device, stream and switch-loop grid, once
+
+// Return DGS_E_DEVICE (with a message) from the enclosing function when a HIP call fails.
+#define DGS_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            ::dgs::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return DGS_E_DEVICE;                                                            \
+        }                                                                                   \
+    } while (0)
+
 size_t loop_record_bytes();
 int loop_grid_size(int device);
 
@@ -59,6 +73,8 @@ hipError_t launch_greedy(const int32_t *A, int32_t n, int32_t *tau, int32_t *sig
 size_t greedy_scratch_bytes(int n);
 hipError_t launch_greedy_rounds(const int32_t *A, int32_t n, int32_t *tau, int32_t *sigma, void *scratch,
                                 int32_t *err, hipStream_t s);
+// p[0..n) = v (a kernel, so that it can sit in a captured graph)
+hipError_t launch_fill(int32_t *p, int32_t n, int32_t v, hipStream_t s);
 hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, int32_t *flag,
                                  hipStream_t s);
 hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t n, hipStream_t s);

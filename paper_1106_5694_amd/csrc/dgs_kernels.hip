@@ -506,6 +506,12 @@ hipError_t launch_greedy(const int32_t *A, int32_t n, int32_t *tau, int32_t *sig
     return hipGetLastError();
 }
 
+hipError_t launch_fill(int32_t *p, int32_t n, int32_t v, hipStream_t s) {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, int32_t *flag,
                                  hipStream_t s) {
     unsigned blocks = (unsigned)((n + 255) / 256);

@@ -204,3 +204,14 @@ def batch_instances(count: int = 512, lo: int = 64, hi: int = 2048, seed: int = 
     ``seed * 1_000_003 + b`` for its matrix."""
     ns = loguniform_sizes(count, lo, hi, seed)
     return [uniform_matrix(int(n), 0, vmax, seed * 1_000_003 + b) for b, n in enumerate(ns)]
+
+
+def serving_trace(duration: float, rate: float = 200.0, lo: int = 128, hi: int = 16384, seed: int = 1,
+                  pool: int = 64):
+    """Serving workload: Poisson arrivals of ``rate`` per second on [0, duration).
+
+    Request k uses instance ``k % pool`` of a pool whose sizes are drawn
+    log-uniform in [lo, hi]; pool instance p is ``lowrank_matrix(ns[p],
+    seed * 1_000_003 + p)``.  Returns (arrival times, pool sizes).
+    """
+    return poisson_arrivals(rate, duration, seed), loguniform_sizes(pool, lo, hi, seed)
