@@ -89,6 +89,7 @@ typedef struct dgs_result {
     int64_t total_benefit;   /* f of the returned assignment */
     int64_t switches;        /* number of 2-exchanges applied */
     int64_t rescans;         /* full re-evaluations of agents during switching */
+    int64_t stalls;          /* switching rounds that applied no switch (waited for a re-evaluation) */
     float device_ms;         /* device time of the solve (HIP events) */
     float phase_ms[DGS_NUM_PHASES]; /* per-phase device time (DGS_PROFILE only, else 0) */
 } dgs_result;

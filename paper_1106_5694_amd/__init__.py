@@ -58,12 +58,13 @@ class Result(ctypes.Structure):
                 ("total_benefit", ctypes.c_int64),
                 ("switches", ctypes.c_int64),
                 ("rescans", ctypes.c_int64),
+                ("stalls", ctypes.c_int64),
                 ("device_ms", ctypes.c_float),
                 ("phase_ms", ctypes.c_float * 5)]
 
     def as_dict(self):
         return dict(initial_benefit=int(self.initial_benefit), total_benefit=int(self.total_benefit),
-                    switches=int(self.switches), rescans=int(self.rescans),
+                    switches=int(self.switches), rescans=int(self.rescans), stalls=int(self.stalls),
                     device_ms=float(self.device_ms),
                     phase_ms={p: float(self.phase_ms[i]) for i, p in enumerate(PHASES)})
 

@@ -11,6 +11,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -48,6 +49,7 @@ struct Context {
     std::string init_error;
     // Cooperative switch loops need every workgroup resident; one at a time.
     std::mutex loop_mu;
+    bool loop_v2 = false;  // DGS_SWITCH_LOOP=v2: the switching loop with owner re-evaluations
 };
 
 Context g_ctx;
@@ -62,6 +64,8 @@ dgs_status ensure_context() {
             return;
         }
         if (hipGetDevice(&g_ctx.device) != hipSuccess) g_ctx.device = 0;
+        const char *loop = getenv("DGS_SWITCH_LOOP");
+        g_ctx.loop_v2 = loop && std::string(loop) == "v2";
         g_ctx.loop_grid = loop_grid_size(g_ctx.device);
         if (g_ctx.loop_grid < 1) {
             g_ctx.init_status = DGS_E_DEVICE;
@@ -127,7 +131,7 @@ VecLayout vec_layout(int32_t n, int grid) {
     L.stats = take(8 * sizeof(int64_t));
     L.flags = take(4 * sizeof(int32_t));
     const bool ex = n >= 2 && n <= kSwitchExMaxN;
-    L.words = take(ex ? switch_ex_word_bytes(n) : 0);
+    L.words = take(ex ? std::max(switch_ex_word_bytes(n), switch_v3_word_bytes(n)) : 0);
     L.replica = take(ex ? switch_ex_replica_bytes(n) : 0);
     L.greedy = take(greedy_scratch_bytes(n));
     L.scan = take(scan_pairs_scratch_bytes(n));
@@ -305,7 +309,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     }
     DGS_HIP(mark(DGS_PHASE_LAYOUT));
     DGS_HIP(launch_transpose(A, I.AT, n, s));
-    DGS_HIP(launch_build_w(A, I.tau, n, I.W, I.d, I.stats + 2, s));
+    DGS_HIP(launch_build_w(A, I.AT, I.tau, n, I.W, I.d, I.stats + 2, s));
     DGS_HIP(mark(DGS_PHASE_SCAN));
     DGS_HIP(launch_scan_pairs(I, I.scan, s));
     DGS_HIP(mark(DGS_PHASE_SWITCH));
@@ -317,8 +321,13 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         if (c.coop) lk.lock();
         if (n >= 2 && n <= kSwitchExMaxN) {
             // stale round tags must not match rounds 0 and 1
-            DGS_HIP(hipMemsetAsync(I.words, 0xFF, switch_ex_word_bytes(n), s));
-            DGS_HIP(launch_switch_ex(I, c.max_switches, I.words, I.replica, I.flags + 2, c.coop, s));
+            if (g_ctx.loop_v2) {
+                DGS_HIP(hipMemsetAsync(I.words, 0xFF, switch_ex_word_bytes(n), s));
+                DGS_HIP(launch_switch_ex(I, c.max_switches, I.words, I.replica, I.flags + 2, c.coop, s));
+            } else {
+                DGS_HIP(hipMemsetAsync(I.words, 0xFF, switch_v3_word_bytes(n), s));
+                DGS_HIP(launch_switch_v3(I, c.max_switches, I.words, I.flags + 2, c.coop, s));
+            }
         } else if (n > kSwitchExMaxN) {
             DGS_HIP(launch_switch_loop(I, c.max_switches, grid, s));
         }
@@ -360,6 +369,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         res->total_benefit = hs[2] + hs[1];
         res->switches = hs[0];
         res->rescans = hs[3];
+        res->stalls = hs[4];
         res->device_ms = ms;
         for (int i = 0; i < DGS_NUM_PHASES; ++i) {
             float pm = 0.f;
@@ -572,6 +582,12 @@ dgs_status check_common(const int32_t *benefit, int32_t n, const void *out) {
 }
 
 }  // namespace
+
+int switch_loop_grid(int n) {
+    if (n < 2) return 0;
+    if (n > kSwitchExMaxN) return g_ctx.loop_grid;
+    return g_ctx.loop_v2 ? switch_ex_grid(n) : switch_v3_grid(n);
+}
 
 int device_cus() {
     int cus = 0;

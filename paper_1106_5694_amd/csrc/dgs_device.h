@@ -22,10 +22,75 @@ __device__ __forceinline__ int key_index(u64 k) { return (int)(~(uint32_t)k); }
 __device__ __forceinline__ u64 umax64(u64 a, u64 b) { return a > b ? a : b; }
 __device__ __forceinline__ u64 umin64(u64 a, u64 b) { return a < b ? a : b; }
 
+// ---- wave64 lane exchanges on the VALU (no LDS round trip) -----------------
+// xor_lanes<J>(v) is the value of lane (lane ^ J): J = 1, 2 are DPP quad
+// permutes, J = 8 a DPP rotate by 8 within a 16-lane row, J = 4 one of the
+// two DPP rotates by 4 / 12 (picked by applying the same rotate to the lane
+// index, so the result does not depend on the rotate's direction), and
+// J = 16, 32 the gfx950 permlane swaps.  Every lane of the wave must be
+// active.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+
+template <int J>
+__device__ __forceinline__ uint32_t xor_lanes(uint32_t v) {
+    if constexpr (J == 1) {
+        return dpp32<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+    } else if constexpr (J == 2) {
+        return dpp32<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    } else if constexpr (J == 4) {
+        const uint32_t lane = threadIdx.x & 63;
+        const uint32_t a = dpp32<0x124>(v), b = dpp32<0x12C>(v);  // row_ror 4, row_ror 12
+        return dpp32<0x124>(lane) == (lane ^ 4u) ? a : b;
+    } else if constexpr (J == 8) {
+        return dpp32<0x128>(v);  // row_ror 8
+    } else if constexpr (J == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
+    } else {
+        static_assert(J == 32, "lane distance");
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? r[0] : r[1];
+    }
+}
+
+template <int J>
+__device__ __forceinline__ u64 xor_lanes64(u64 v) {
+    return ((u64)xor_lanes<J>((uint32_t)(v >> 32)) << 32) | (u64)xor_lanes<J>((uint32_t)v);
+}
+
+// The value of lane (lane ^ mask).  In unrolled loops the mask is a
+// constant and the switch folds to one xor_lanes; other masks go through
+// ds_bpermute.
 __device__ __forceinline__ u64 shfl_xor64(u64 v, int mask) {
-    int lo = __shfl_xor((int)(uint32_t)v, mask, 64);
-    int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
+    switch (mask) {
+        case 1: return xor_lanes64<1>(v);
+        case 2: return xor_lanes64<2>(v);
+        case 4: return xor_lanes64<4>(v);
+        case 8: return xor_lanes64<8>(v);
+        case 16: return xor_lanes64<16>(v);
+        case 32: return xor_lanes64<32>(v);
+        default: break;
+    }
+    const int lo = __shfl_xor((int)(uint32_t)v, mask, 64);
+    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
     return ((u64)(uint32_t)hi << 32) | (u64)(uint32_t)lo;
+}
+
+// Lane `lane`'s value (lane uniform across the wave), through SGPRs.
+__device__ __forceinline__ u64 readlane64(u64 v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((u64)hi << 32) | lo;
+}
+
+// The value of lane 63 - lane (row mirror, then the 16- and 32-lane swaps).
+__device__ __forceinline__ u64 reverse_lanes64(u64 v) {
+    const uint32_t lo = xor_lanes<32>(xor_lanes<16>(dpp32<0x140>((uint32_t)v)));
+    const uint32_t hi = xor_lanes<32>(xor_lanes<16>(dpp32<0x140>((uint32_t)(v >> 32))));
+    return ((u64)hi << 32) | lo;
 }
 
 // Top-2 of a set of unique keys (0 = empty slot).

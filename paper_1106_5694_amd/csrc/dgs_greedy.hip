@@ -56,10 +56,7 @@ __device__ __forceinline__ u64 wave_bitonic_desc(u64 v, int lane) {
 
 // Top kRound of the union of two descending lists (one key per lane each).
 __device__ __forceinline__ u64 wave_merge_top(u64 a, u64 b, int lane) {
-    const int src = 63 - lane;
-    const u64 brev = ((u64)(uint32_t)__shfl((int)(uint32_t)(b >> 32), src, 64) << 32) |
-                     (u64)(uint32_t)__shfl((int)(uint32_t)b, src, 64);
-    return wave_bitonic_desc(kmax(a, brev), lane);
+    return wave_bitonic_desc(kmax(a, reverse_lanes64(b)), lane);
 }
 
 struct TopkParams {
@@ -114,16 +111,14 @@ __global__ __launch_bounds__(kTopkBlock) void k_greedy_topk(TopkParams P) {
                 while (mm) {
                     const int src = __ffsll((long long)mm) - 1;
                     mm &= mm - 1;
-                    const u64 k = ((u64)(uint32_t)__shfl((int)(uint32_t)(key >> 32), src, 64) << 32) |
-                                  (u64)(uint32_t)__shfl((int)(uint32_t)key, src, 64);
+                    const u64 k = readlane64(key, src);
                     // insert k into the descending list: lanes below k shift down by one
                     const u64 up = ((u64)(uint32_t)__shfl_up((int)(uint32_t)(list >> 32), 1, 64) << 32) |
                                    (u64)(uint32_t)__shfl_up((int)(uint32_t)list, 1, 64);
                     if (list < k) list = (lane == 0 || up > k) ? k : up;
                 }
             }
-            lmin = ((u64)(uint32_t)__shfl((int)(uint32_t)(list >> 32), 63, 64) << 32) |
-                   (u64)(uint32_t)__shfl((int)(uint32_t)list, 63, 64);
+            lmin = readlane64(list, 63);
         }
     }
     wl[w][lane] = list;
@@ -162,33 +157,44 @@ __global__ __launch_bounds__(256) void k_greedy_resolve(ResolveParams P) {
     __syncthreads();
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
+        const int chunks = P.chunks;
+        // the lists of agent ri + 1 are read while agent ri is resolved
+        u64 nxt[kMaxChunks];
+#pragma unroll
+        for (int p = 0; p < kMaxChunks; ++p) nxt[p] = p < chunks ? L[(size_t)p * 64 + lane] : 0;
+        int my_pick = -1;  // lane ri keeps agent ri's choice
         for (int ri = 0; ri < P.rows; ++ri) {
+            u64 cur[kMaxChunks];
+#pragma unroll
+            for (int p = 0; p < kMaxChunks; ++p) cur[p] = nxt[p];
+            if (ri + 1 < P.rows) {
+#pragma unroll
+                for (int p = 0; p < kMaxChunks; ++p)
+                    nxt[p] = p < chunks ? L[((size_t)(ri + 1) * chunks + p) * 64 + lane] : 0;
+            }
+            uint32_t word[kMaxChunks];
+#pragma unroll
+            for (int p = 0; p < kMaxChunks; ++p) {
+                const int c = cur[p] ? key_index(cur[p]) : 0;
+                word[p] = tk[c >> 5];
+            }
             u64 best = 0;
-            for (int p = 0; p < P.chunks; ++p) {
-                const u64 v = L[((size_t)ri * P.chunks + p) * 64 + lane];
-                const int c = v ? key_index(v) : 0;
-                const bool fr = v != 0 && !((tk[c >> 5] >> (c & 31)) & 1u);
+#pragma unroll
+            for (int p = 0; p < kMaxChunks; ++p) {
+                const int c = cur[p] ? key_index(cur[p]) : 0;
+                const bool fr = cur[p] != 0 && !((word[p] >> (c & 31)) & 1u);
                 const unsigned long long m = __ballot(fr);
-                if (m) {
-                    const int src = __ffsll((long long)m) - 1;
-                    const u64 cand = ((u64)(uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64) << 32) |
-                                     (u64)(uint32_t)__shfl((int)(uint32_t)v, src, 64);
-                    best = kmax(best, cand);
-                }
+                if (m) best = kmax(best, readlane64(cur[p], __ffsll((long long)m) - 1));
             }
             if (best == 0) {  // cannot happen (see above); never index with it
-                if (lane == 0) {
-                    atomicOr(P.err, 4);
-                    pick[ri] = -1;
-                }
+                if (lane == 0) atomicOr(P.err, 4);
                 continue;
             }
             const int c = key_index(best);
-            if (lane == 0) {
-                tk[c >> 5] |= 1u << (c & 31);
-                pick[ri] = c;
-            }
+            if (lane == 0) atomicOr(&tk[c >> 5], 1u << (c & 31));
+            if (lane == ri) my_pick = c;
         }
+        pick[lane] = my_pick;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < words; i += blockDim.x) P.taken[i] = tk[i];

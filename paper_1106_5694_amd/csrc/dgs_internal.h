@@ -78,8 +78,9 @@ hipError_t launch_fill(int32_t *p, int32_t n, int32_t v, hipStream_t s);
 hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, int32_t *flag,
                                  hipStream_t s);
 hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t n, hipStream_t s);
-hipError_t launch_build_w(const int32_t *A, const int32_t *tau, int32_t n, int32_t *W, int32_t *d,
-                          int64_t *f0, hipStream_t s);
+// W from AT (built first) and tau; d and f0 from A.
+hipError_t launch_build_w(const int32_t *A, const int32_t *AT, const int32_t *tau, int32_t n, int32_t *W,
+                          int32_t *d, int64_t *f0, hipStream_t s);
 hipError_t launch_scan_rows(const Instance &I, hipStream_t s);
 // Symmetric tile-pair difference evaluation (dgs_scan.hip).
 size_t scan_pairs_scratch_bytes(int n);
@@ -96,6 +97,15 @@ size_t switch_ex_replica_bytes(int n);
 // other persistent work on the device.
 hipError_t launch_switch_ex(const Instance &I, int64_t max_switches, void *words, void *replica, int32_t *err,
                             bool coop, hipStream_t s);
+
+// Switching loop with cooperative re-evaluation (dgs_switch3.hip), for 2 <= n <= kSwitchExMaxN:
+// grid of switch_v3_grid(n) workgroups, exchange words of switch_v3_word_bytes(n) (set to 0xFF first).
+int switch_v3_grid(int n);
+size_t switch_v3_word_bytes(int n);
+hipError_t launch_switch_v3(const Instance &I, int64_t max_switches, void *words, int32_t *err, bool coop,
+                            hipStream_t s);
+// Workgroups the switching loop of an n-agent solve keeps resident.
+int switch_loop_grid(int n);
 
 // Internal entry points used by the server (dgs_api.cpp).
 dgs_status solve_internal(const int32_t *benefit, int32_t n, int32_t *assign_out, int64_t max_switches, bool dev,

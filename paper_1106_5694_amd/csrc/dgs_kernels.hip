@@ -108,19 +108,40 @@ __global__ __launch_bounds__(256) void k_transpose(const int32_t *__restrict__ A
     }
 }
 
-// W[r][c] = a[r][tau(c)], d[r] = a[r][tau(r)], f0 += d[r].
-__global__ __launch_bounds__(256) void k_build_w(const int32_t *__restrict__ A, const int32_t *__restrict__ tau,
-                                                   int n, int32_t *__restrict__ W, int32_t *d,
-                                                   unsigned long long *f0) {
-    const int r = blockIdx.x;
-    const int32_t *Ar = A + (int64_t)r * n;
-    int32_t *Wr = W + (int64_t)r * n;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) Wr[c] = Ar[tau[c]];
-    if (threadIdx.x == 0) {
-        int v = Ar[tau[r]];
-        d[r] = v;
-        atomicAdd(f0, (unsigned long long)(long long)v);
+// W[r][c] = a[r][tau(c)] = AT[tau(c)][r]: a transpose whose source rows are
+// picked through tau.  Each 64 x 64 tile reads 64 row segments of AT and
+// writes 64 row segments of W, both coalesced, through an LDS tile.
+__global__ __launch_bounds__(256) void k_build_w(const int32_t *__restrict__ AT, const int32_t *__restrict__ tau,
+                                                   int n, int32_t *__restrict__ W) {
+    __shared__ int32_t tile[64][65];
+    const int bx = blockIdx.x * 64, by = blockIdx.y * 64;  // bx: agents r, by: agents c
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int c = ty; c < 64; c += 4) {
+        const int cc = by + c, rr = bx + tx;
+        if (cc < n && rr < n) tile[c][tx] = AT[(int64_t)tau[cc] * n + rr];
     }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int rr = bx + r, cc = by + tx;
+        if (rr < n && cc < n) W[(int64_t)rr * n + cc] = tile[tx][r];
+    }
+}
+
+// d[r] = a[r][tau(r)] and f0 = sum of d.
+__global__ __launch_bounds__(256) void k_benefits(const int32_t *__restrict__ A, const int32_t *__restrict__ tau,
+                                                    int n, int32_t *d, unsigned long long *f0) {
+    __shared__ long long part[4];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    long long v = 0;
+    if (r < n) {
+        const int x = A[(int64_t)r * n + tau[r]];
+        d[r] = x;
+        v = x;
+    }
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(f0, (unsigned long long)(part[0] + part[1] + part[2] + part[3]));
 }
 
 // ---- difference evaluation of every agent (Algorithm 2) ---------------------------
@@ -526,9 +547,11 @@ hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t n, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_build_w(const int32_t *A, const int32_t *tau, int32_t n, int32_t *W, int32_t *d,
-                          int64_t *f0, hipStream_t s) {
-    hipLaunchKernelGGL(k_build_w, dim3((unsigned)n), dim3(256), 0, s, A, tau, n, W, d,
+hipError_t launch_build_w(const int32_t *A, const int32_t *AT, const int32_t *tau, int32_t n, int32_t *W,
+                          int32_t *d, int64_t *f0, hipStream_t s) {
+    const unsigned t = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL(k_build_w, dim3(t, t), dim3(256), 0, s, AT, tau, n, W);
+    hipLaunchKernelGGL(k_benefits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, tau, n, d,
                        (unsigned long long *)f0);
     return hipGetLastError();
 }

@@ -53,7 +53,7 @@ constexpr int kLargeWorkers = 4;
 // Workgroups the switching loop of an n-agent request keeps resident.
 int loop_wgs(int32_t n) {
     if (n <= dgs::kBatchMaxN) return 0;
-    return dgs::switch_ex_grid(n);
+    return dgs::switch_loop_grid(n);
 }
 
 }  // namespace

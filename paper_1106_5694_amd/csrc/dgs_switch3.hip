@@ -1,0 +1,589 @@
+// Switching phase of DGS on gfx950 (Section 3.3, Algorithm 1 read as
+// steepest ascent: every round applies the best 2-exchange over all agents,
+// until none improves the objective), with cooperative re-evaluation.
+//
+// Grid: G = ceil(n / 256) workgroups of 256 threads.  Thread t of workgroup
+// q owns agent r = 256 q + t and keeps in registers its job tau(r), its
+// benefit d(r) = a[r][tau(r)] and its candidate list: up to kM exact
+// candidates (gain, job, partner agent) and a bound that no candidate
+// outside the list exceeds, so a non-empty list's maximum is the agent's
+// exact best exchange.  The benefit matrix and its transpose are read-only;
+// everything a workgroup learns about other agents comes through the
+// per-round exchange of words.
+//
+// Exchange: per round every workgroup writes kW 64-bit words and reads all
+// workgroups' words.  Each word carries the round number in its low 8 bits
+// and is written and read with relaxed agent-scope atomics; the words are
+// double-buffered by round parity, so a word is current exactly when its tag
+// matches and no fences are needed.
+//
+// A workgroup's words: its best exchange (over its agents' lists, with the
+// job, partner and own job of that exchange), its most promising pending
+// agent (an agent whose list ran empty while its bound still promises a
+// positive gain) with that agent's job and benefit, and its top-2 "shares"
+// for each target of the round.  The share for target x is the best two of
+// g(r, x) over the workgroup's agents r.  Because g(r, x) = g(x, r), the
+// shares of all workgroups together are x's full re-evaluation: x's new list
+// holds the workgroup bests above the largest workgroup second, and that
+// second bounds everything else.  Targets are the two agents switched in
+// the previous round (their candidates all change) and up to kD pending
+// agents chosen in the previous round, largest bound first.  No agent is
+// ever re-evaluated by one workgroup alone.
+//
+// Decision (identical in every workgroup, computed from the words alone):
+// the best exchange among the workgroup bests and the targets' new bests.
+// If a pending agent's bound beats it, the round applies nothing (a stall);
+// that agent is a target of this round and exact in the next one.
+// Otherwise the switch (i*, j*) with partner k = sigma(j*) is applied and
+// every other agent r receives its two changed candidates exactly:
+// g(r, i*) for job j* and g(r, k) for job tau(i*).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dgs_device.h"
+#include "dgs_internal.h"
+
+namespace dgs {
+namespace {
+
+using namespace dev;
+
+constexpr int kT = 256;                     // threads = agents per workgroup
+constexpr int kM = 8;                       // candidate list length
+constexpr int kD = 8;                       // pending agents re-evaluated per round
+constexpr int kTargets = 2 + kD;            // share targets per round
+constexpr int kWBest = 0, kWPay = 1, kWPend = 2, kWInfo = 3, kWShare = 4;
+constexpr int kW = kWShare + 2 * kTargets;  // words per workgroup per round
+constexpr int kVals = 2 + kTargets;         // per-thread values reduced at the top of a round
+constexpr int kMaxG = 256;                  // n <= 65535
+constexpr int kGatherPer = (kMaxG * kW + kT - 1) / kT;
+constexpr int kCand = kMaxG;
+constexpr long long kSpinLimit = 1ll << 27;
+constexpr int kItems = 1 + 2 * kTargets;    // maxima over workgroups taken per round
+
+// ---- keys ------------------------------------------------------------------------------
+// List entry: gain^bias:32 | 0xFFFF-job:16 | partner agent:16.  Agent key:
+// gain^bias:32 | 0xFFFF-agent:16 | 0:16.  In both, unsigned order of the
+// upper 48 bits is (gain ascending, index descending); 0 = none.
+__device__ __forceinline__ u64 gbias(int g) { return (u64)((uint32_t)g ^ 0x80000000u) << 32; }
+__device__ __forceinline__ u64 le_key(int g, int job, int partner) {
+    return gbias(g) | ((u64)(0xFFFFu - (uint32_t)job) << 16) | (u64)(uint32_t)partner;
+}
+__device__ __forceinline__ u64 ak_key(int g, int agent) {
+    return gbias(g) | ((u64)(0xFFFFu - (uint32_t)agent) << 16);
+}
+__device__ __forceinline__ int kgain(u64 k) { return (int)((uint32_t)(k >> 32) ^ 0x80000000u); }
+__device__ __forceinline__ int kidx(u64 k) { return (int)(0xFFFFu - (uint32_t)((k >> 16) & 0xFFFFu)); }
+__device__ __forceinline__ int kpartner(u64 k) { return (int)(k & 0xFFFFu); }
+__device__ __forceinline__ u64 hi48(u64 k) { return k & ~(u64)0xFFFF; }
+
+// ---- wave64 reductions on the DPP path -----------------------------------------------
+// quad_perm xor 1, quad_perm xor 2, reversal within 8 lanes, reversal within
+// 16 lanes: each pairs disjoint groups of lanes that already agree, so after
+// the four steps every lane of a 16-lane row holds the row's result; the
+// four rows are combined through readlane.  Call with all 64 lanes active.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ u64 dpp64(u64 v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, true);
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ u64 lane64(u64 v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ u64 wave_max(u64 v) {
+    v = umax64(v, dpp64<kDppXor1>(v));
+    v = umax64(v, dpp64<kDppXor2>(v));
+    v = umax64(v, dpp64<kDppHalfMirror>(v));
+    v = umax64(v, dpp64<kDppMirror>(v));
+    return umax64(umax64(lane64(v, 0), lane64(v, 16)), umax64(lane64(v, 32), lane64(v, 48)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ void top2_step(u64 &a1, u64 &a2) {
+    const u64 b1 = dpp64<CTRL>(a1), b2 = dpp64<CTRL>(a2);
+    top2_merge(a1, a2, b1, b2);
+}
+
+// Top-2 over the wave of keys that are unique apart from zeros.
+__device__ __forceinline__ void wave_top2(u64 &a1, u64 &a2) {
+    top2_step<kDppXor1>(a1, a2);
+    top2_step<kDppXor2>(a1, a2);
+    top2_step<kDppHalfMirror>(a1, a2);
+    top2_step<kDppMirror>(a1, a2);
+    u64 r1 = lane64(a1, 0), r2 = lane64(a2, 0);
+    top2_merge(r1, r2, lane64(a1, 16), lane64(a2, 16));
+    top2_merge(r1, r2, lane64(a1, 32), lane64(a2, 32));
+    top2_merge(r1, r2, lane64(a1, 48), lane64(a2, 48));
+    a1 = r1;
+    a2 = r2;
+}
+
+// ---- candidate lists (registers) --------------------------------------------------------
+
+__device__ __forceinline__ u64 list_max(const u64 (&L)[kM]) {
+    u64 m = L[0];
+#pragma unroll
+    for (int i = 1; i < kM; ++i) m = umax64(m, L[i]);
+    return m;
+}
+
+// Insert exact candidate y; B (upper 48 bits only) bounds every candidate
+// outside the list.  y's job is not in the list.
+__device__ __forceinline__ void list_insert(u64 (&L)[kM], u64 &B, u64 y) {
+    const u64 yh = hi48(y);
+    if (yh <= B) return;
+    u64 mn = L[0];
+    int mi = 0;
+#pragma unroll
+    for (int i = 1; i < kM; ++i) {
+        if (L[i] < mn) {
+            mn = L[i];
+            mi = i;
+        }
+    }
+    if (mn != 0) {
+        if (yh < hi48(mn)) {  // below every entry of a full list: stays outside
+            B = yh;
+            return;
+        }
+        B = umax64(B, hi48(mn));  // evict the smallest entry
+    }
+#pragma unroll
+    for (int i = 0; i < kM; ++i)
+        if (i == mi) L[i] = y;
+}
+
+__device__ __forceinline__ void list_drop_jobs(u64 (&L)[kM], int j1, int j2) {
+#pragma unroll
+    for (int i = 0; i < kM; ++i) {
+        const int j = kidx(L[i]);
+        if (L[i] != 0 && (j == j1 || j == j2)) L[i] = 0;
+    }
+}
+
+// Entries of rank 0..kM (largest first) among cand[0..cnt) go to sel[rank];
+// sel[0..kM] must be zero beforehand.  Upper 48 bits are unique.
+__device__ __forceinline__ void rank_select(const u64 *cand, int cnt, u64 *sel) {
+    for (int e = threadIdx.x; e < cnt; e += kT) {
+        const u64 me = hi48(cand[e]);
+        int rank = 0;
+        for (int i = 0; i < cnt; ++i) rank += hi48(cand[i]) > me;
+        if (rank <= kM) sel[rank] = cand[e];
+    }
+}
+
+struct V3Params {
+    const int32_t *A;
+    const int32_t *AT;
+    int32_t *tau;          // in: start assignment; out: final assignment
+    const int32_t *sigma;  // start inverse assignment
+    const int32_t *d;      // start benefits d[c] = a[c][tau(c)]
+    const u64 *lists;      // full-evaluation candidate lists [n][kScanListLen] (gain, job) keys
+    const u64 *bb;         // full-evaluation bounds
+    u64 *words;            // 2 * G * kW exchange words
+    int64_t *stats;        // [0] switches [1] gain sum [3] re-evaluations [4] stalled rounds
+    const int32_t *flags;  // [0] != 0: range check failed, do nothing
+    int32_t *err;          // set when a wait exceeds its spin limit (1) or a decision is invalid (2)
+    int n;
+    int64_t max_switches;
+};
+
+__device__ __forceinline__ void put_word(u64 *p, u64 w) {
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
+    extern __shared__ __align__(16) u64 wl[];  // G * kW gathered words
+    __shared__ u64 vals[kVals][kT];
+    __shared__ u64 pay[kT];    // job, partner and own job of each agent's best exchange
+    __shared__ u64 pinfo[kT];  // benefit and job of each agent
+    __shared__ u64 dec[kItems];
+    __shared__ u64 cand[kCand];
+    __shared__ u64 sel[kM + 1];
+    __shared__ int cand_n;
+    __shared__ int s_err;
+    __shared__ int tg_agent[kTargets], tg_tau[kTargets];  // this round's targets
+    __shared__ int nx_agent[kD], nx_tau[kD], nx_d[kD];    // pending agents chosen this round
+    __shared__ u64 nx_key[kD];
+
+    if (P.flags[0]) return;  // same decision in every workgroup
+    const int G = gridDim.x, q = blockIdx.x, t = threadIdx.x, n = P.n;
+    const int64_t nn = n;
+    const int r = q * kT + t;
+    const bool mine = r < n;
+    const int lane = t & 63, wave = t >> 6;
+
+    int tr = 0, dr = 0;
+    u64 L[kM];
+#pragma unroll
+    for (int i = 0; i < kM; ++i) L[i] = 0;
+    u64 B = 0;
+    bool inflight = false;
+    if (mine) {
+        tr = P.tau[r];
+        dr = P.d[r];
+#pragma unroll
+        for (int i = 0; i < kM && i < kScanListLen; ++i) {
+            const u64 k = P.lists[(size_t)r * kScanListLen + i];
+            if (k) {
+                const int job = key_index(k);
+                L[i] = le_key(key_gain(k), job, P.sigma[job]);
+            }
+        }
+        const u64 b = P.bb[r];
+        B = b ? hi48(le_key(key_gain(b), key_index(b), 0)) : 0;
+    }
+    if (t == 0) s_err = 0;
+    if (t < kTargets) tg_agent[t] = -1;
+    if (t < kD) nx_agent[t] = -1;
+    u64 sh[kTargets];
+#pragma unroll
+    for (int i = 0; i < kTargets; ++i) sh[i] = 0;
+    int64_t S = 0, gsum = 0, refreshes = 0, stalls = 0;
+    __syncthreads();
+
+    for (uint32_t s = 0;; ++s) {
+        const uint32_t tag = s & 0xFFu;
+        u64 *buf = P.words + (size_t)(s & 1) * G * kW;
+
+        // ---- this workgroup's words ------------------------------------------------------
+        {
+            u64 lk = 0, pd = 0;
+            if (mine) {
+                const u64 b = list_max(L);
+                if (b) {
+                    lk = ak_key(kgain(b), r);
+                } else if (!inflight && B != 0 && kgain(B) > 0) {
+                    pd = ak_key(kgain(B), r);
+                }
+                pay[t] = ((u64)(uint32_t)kidx(b) << 48) | ((u64)(uint32_t)kpartner(b) << 32) |
+                         ((u64)(uint32_t)tr << 16);
+                pinfo[t] = ((u64)(uint32_t)dr << 32) | ((u64)(uint32_t)tr << 16);
+            }
+            vals[0][t] = lk;
+            vals[1][t] = pd;
+#pragma unroll
+            for (int i = 0; i < kTargets; ++i) vals[2 + i][t] = sh[i];
+        }
+        __syncthreads();
+        // wave w reduces value types w, w + 4, w + 8 and writes their words
+        for (int ty = wave; ty < kVals; ty += 4) {
+            if (ty < 2) {
+                u64 a = umax64(umax64(vals[ty][lane], vals[ty][lane + 64]),
+                               umax64(vals[ty][lane + 128], vals[ty][lane + 192]));
+                a = wave_max(a);
+                if (lane == 0) {
+                    u64 w1 = 0;
+                    if (a) w1 = (ty == 0 ? pay : pinfo)[kidx(a) - q * kT];
+                    put_word(&buf[(size_t)q * kW + (ty == 0 ? kWBest : kWPend)], a | tag);
+                    put_word(&buf[(size_t)q * kW + (ty == 0 ? kWPay : kWInfo)], (w1 & ~(u64)0xFF) | tag);
+                }
+            } else {
+                u64 a1 = vals[ty][lane], a2 = 0;
+                top2_push(a1, a2, vals[ty][lane + 64]);
+                top2_push(a1, a2, vals[ty][lane + 128]);
+                top2_push(a1, a2, vals[ty][lane + 192]);
+                wave_top2(a1, a2);
+                if (lane < 2) {
+                    const u64 v = lane == 0 ? a1 : a2;
+                    const u64 w = v ? (hi48(v) | ((v & 0xFF) << 8)) : 0;  // local partner in bits 15..8
+                    put_word(&buf[(size_t)q * kW + kWShare + 2 * (ty - 2) + lane], w | tag);
+                }
+            }
+        }
+
+        // ---- gather every workgroup's words ------------------------------------------------
+        {
+            const int NW = G * kW;
+            u64 wv[kGatherPer];
+#pragma unroll
+            for (int i = 0; i < kGatherPer; ++i) {
+                const int x = t + i * kT;
+                wv[i] = x < NW ? __hip_atomic_load(&buf[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (u64)tag;
+            }
+            long long spins = 0;
+            for (;;) {
+                bool ready = true;
+#pragma unroll
+                for (int i = 0; i < kGatherPer; ++i) ready &= (uint32_t)(wv[i] & 0xFFu) == tag;
+                if (ready) break;
+                if (++spins > kSpinLimit) {
+                    s_err = 1;
+                    atomicOr(P.err, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int i = 0; i < kGatherPer; ++i) {
+                    const int x = t + i * kT;
+                    if (x < NW && (uint32_t)(wv[i] & 0xFFu) != tag)
+                        wv[i] = __hip_atomic_load(&buf[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kGatherPer; ++i) {
+                const int x = t + i * kT;
+                if (x < NW) wl[x] = wv[i];
+            }
+        }
+        __syncthreads();
+        if (s_err) break;
+
+        // ---- maxima over workgroups and the pending agents to re-evaluate ----------------
+        // item 0: best exchange; 1 + T: best share of target T; 1 + kTargets + T:
+        // second share of target T (needed by the target's owner only).  Each
+        // maximum carries the index of the workgroup it came from in bits 7..0.
+        for (int it = wave; it < kItems; it += 4) {
+            int widx;
+            if (it == 0) {
+                widx = kWBest;
+            } else if (it <= kTargets) {
+                widx = kWShare + 2 * (it - 1);
+            } else {
+                const int T = it - 1 - kTargets;
+                const int x = tg_agent[T];
+                if (x < 0 || x / kT != q) continue;
+                widx = kWShare + 2 * T + 1;
+            }
+            u64 m = 0;
+            for (int qq = lane; qq < G; qq += 64) m = umax64(m, (wl[qq * kW + widx] & ~(u64)0xFF) | (u64)qq);
+            m = wave_max(m);
+            if (lane == 0) dec[it] = m;
+        }
+        if (t < G) {
+            const u64 me = hi48(wl[t * kW + kWPend]);
+            if (me) {
+                int rank = 0;
+                for (int qq = 0; qq < G; ++qq) rank += hi48(wl[qq * kW + kWPend]) > me;
+                if (rank < kD) {
+                    const u64 info = wl[t * kW + kWInfo];
+                    nx_key[rank] = me;
+                    nx_agent[rank] = kidx(me);
+                    nx_tau[rank] = (int)((info >> 16) & 0xFFFFu);
+                    nx_d[rank] = (int)(uint32_t)(info >> 32);
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- the best exchange --------------------------------------------------------------
+        u64 best = 0;
+        int bj = -1, bk = -1, bj0 = -1;  // job, partner and own job of the best exchange
+        {
+            const u64 mb = dec[0];
+            if (hi48(mb)) {
+                const int a = kidx(mb);
+                const u64 pw = wl[(a / kT) * kW + kWPay];
+                best = hi48(mb);
+                bj = (int)((pw >> 48) & 0xFFFFu);
+                bk = (int)((pw >> 32) & 0xFFFFu);
+                bj0 = (int)((pw >> 16) & 0xFFFFu);
+            }
+        }
+        for (int T = 0; T < kTargets; ++T) {
+            const int x = tg_agent[T];
+            const u64 m = dec[1 + T];
+            if (x < 0 || hi48(m) == 0) continue;
+            const u64 c = ak_key(kgain(m), x);
+            if (c > best) {
+                best = c;
+                bj = kidx(m);
+                bk = (int)(m & 0xFF) * kT + (int)((m >> 8) & 0xFF);
+                bj0 = tg_tau[T];
+            }
+        }
+
+        // ---- owners rebuild the lists of this round's targets ------------------------------
+        for (int T = 0; T < kTargets; ++T) {
+            const int x = tg_agent[T];
+            if (x < 0 || x / kT != q) continue;  // uniform across the workgroup
+            const u64 bnd = hi48(dec[1 + kTargets + T]);
+            if (t == 0) cand_n = 0;
+            if (t <= kM) sel[t] = 0;
+            __syncthreads();
+            if (t < G) {
+                const u64 w = wl[t * kW + kWShare + 2 * T];
+                if (hi48(w) > bnd) cand[atomicAdd(&cand_n, 1)] = hi48(w) | (u64)(t * kT + (int)((w >> 8) & 0xFF));
+            }
+            __syncthreads();
+            rank_select(cand, cand_n, sel);
+            __syncthreads();
+            if (r == x) {
+#pragma unroll
+                for (int i = 0; i < kM; ++i) L[i] = sel[i];
+                B = umax64(bnd, hi48(sel[kM]));
+                inflight = false;
+            }
+            __syncthreads();
+        }
+
+        // ---- decide ---------------------------------------------------------------------------
+        if (P.max_switches >= 0 && S >= P.max_switches) break;
+        const bool stall = nx_agent[0] >= 0 && nx_key[0] > best;  // pending bounds have gain > 0
+        if (!stall && (best == 0 || kgain(best) <= 0)) break;
+
+        int is = -1, js = -1, k = -1, j0 = -1, gw = 0, dis = 0, dk = 0;
+        if (!stall) {
+            is = kidx(best);
+            js = bj;
+            k = bk;
+            j0 = bj0;
+            gw = kgain(best);
+            if (is < 0 || is >= n || js < 0 || js >= n || k < 0 || k >= n || j0 < 0 || j0 >= n || k == is) {
+                if (t == 0) atomicOr(P.err, 2);  // cannot happen; never index with it
+                break;
+            }
+            dis = P.A[(int64_t)is * nn + js];  // a[i*][j*]
+            dk = P.A[(int64_t)k * nn + j0];    // a[k][j0]
+        }
+
+        // ---- loads of this round: the switch's changed candidates and the re-evaluations --
+        int a1 = 0, a2 = 0, w1 = 0, w2 = 0;
+        int tr2 = tr, dr2 = dr;  // job and benefit after this round's switch
+        if (mine && !stall) {
+            if (r == is) {
+                tr2 = js;
+                dr2 = dis;
+            } else if (r == k) {
+                tr2 = j0;
+                dr2 = dk;
+            } else {
+                a1 = P.AT[(int64_t)js * nn + r];  // a[r][j*]
+                a2 = P.AT[(int64_t)j0 * nn + r];  // a[r][j0]
+                w1 = P.A[(int64_t)is * nn + tr];  // a[i*][tau(r)]
+                w2 = P.A[(int64_t)k * nn + tr];   // a[k][tau(r)]
+            }
+        }
+        int ra[kD], rb[kD];
+#pragma unroll
+        for (int dd = 0; dd < kD; ++dd) {
+            const int x = nx_agent[dd];
+            ra[dd] = rb[dd] = 0;
+            if (mine && x >= 0 && x != is && x != k && r != x) {
+                ra[dd] = P.AT[(int64_t)nx_tau[dd] * nn + r];  // a[r][tau(x)]
+                rb[dd] = P.A[(int64_t)x * nn + tr2];          // a[x][tau(r)] after the switch
+            }
+        }
+
+        // ---- apply the switch to this workgroup's agents; shares for next round ----------
+        u64 nsh[kTargets];
+#pragma unroll
+        for (int i = 0; i < kTargets; ++i) nsh[i] = 0;
+        if (!stall) {
+            ++S;
+            gsum += gw;
+            if (mine) {
+                if (r == is) {
+                    nsh[1] = le_key(-gw, js, t);  // g(i*, k) after the switch
+#pragma unroll
+                    for (int i = 0; i < kM; ++i) L[i] = 0;
+                    B = 0;
+                    inflight = false;
+                } else if (r == k) {
+                    nsh[0] = le_key(-gw, j0, t);  // g(k, i*) after the switch
+#pragma unroll
+                    for (int i = 0; i < kM; ++i) L[i] = 0;
+                    B = 0;
+                    inflight = false;
+                } else {
+                    const int g1 = (a1 + w1) - (dr + dis);  // g(r, i*)
+                    const int g2 = (a2 + w2) - (dr + dk);   // g(r, k)
+                    list_drop_jobs(L, js, j0);
+                    list_insert(L, B, le_key(g1, js, is));
+                    list_insert(L, B, le_key(g2, j0, k));
+                    nsh[0] = le_key(g1, tr, t);
+                    nsh[1] = le_key(g2, tr, t);
+                }
+                tr = tr2;
+                dr = dr2;
+            }
+        } else {
+            ++stalls;
+        }
+#pragma unroll
+        for (int dd = 0; dd < kD; ++dd) {
+            const int x = nx_agent[dd];
+            if (mine && x >= 0 && x != is && x != k && r != x)
+                nsh[2 + dd] = le_key((ra[dd] + rb[dd]) - (dr + nx_d[dd]), tr, t);  // g(r, x)
+            if (mine && x == r && r != is && r != k) inflight = true;
+        }
+        int nref = 0;
+#pragma unroll
+        for (int dd = 0; dd < kD; ++dd) {
+            const int x = nx_agent[dd];
+            nref += (x >= 0 && x != is && x != k) ? 1 : 0;
+        }
+        refreshes += nref;
+        __syncthreads();  // every thread has read this round's targets and pending choices
+        if (t < kTargets) {
+            if (t == 0) {
+                tg_agent[0] = is;
+                tg_tau[0] = js;
+            } else if (t == 1) {
+                tg_agent[1] = k;
+                tg_tau[1] = j0;
+            } else {
+                const int dd = t - 2;
+                const int x = nx_agent[dd];
+                tg_agent[t] = (x >= 0 && x != is && x != k) ? x : -1;
+                tg_tau[t] = nx_tau[dd];
+                nx_agent[dd] = -1;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kTargets; ++i) sh[i] = nsh[i];
+    }
+
+    if (mine) P.tau[r] = tr;
+    if (t == 0) {
+        if (q == 0) {
+            P.stats[0] = S;
+            P.stats[1] = gsum;
+            P.stats[3] = refreshes;
+            P.stats[4] = stalls;
+        }
+    }
+}
+
+}  // namespace
+
+int switch_v3_grid(int n) { return (n + kT - 1) / kT; }
+size_t switch_v3_word_bytes(int n) { return 2 * (size_t)switch_v3_grid(n) * kW * sizeof(u64); }
+
+hipError_t launch_switch_v3(const Instance &I, int64_t max_switches, void *words, int32_t *err, bool coop,
+                            hipStream_t s) {
+    V3Params P;
+    P.A = I.A;
+    P.AT = I.AT;
+    P.tau = I.tau;
+    P.sigma = I.sigma;
+    P.d = I.d;
+    P.lists = I.lists;
+    P.bb = I.bb;
+    P.words = (u64 *)words;
+    P.stats = I.stats;
+    P.flags = I.flags;
+    P.err = err;
+    P.n = I.n;
+    P.max_switches = max_switches;
+    const int grid = switch_v3_grid(I.n);
+    if (grid < 1 || grid > kMaxG) return hipErrorInvalidValue;
+    const size_t shm = (size_t)grid * kW * sizeof(u64);
+    hipError_t e = hipFuncSetAttribute((const void *)k_switch_v3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    if (!coop) {
+        hipLaunchKernelGGL(k_switch_v3, dim3((unsigned)grid), dim3(kT), shm, s, P);
+        return hipGetLastError();
+    }
+    void *args[] = {&P};
+    return hipLaunchCooperativeKernel((const void *)k_switch_v3, dim3((unsigned)grid), dim3(kT), args, (unsigned)shm, s);
+}
+
+}  // namespace dgs
