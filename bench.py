@@ -41,8 +41,8 @@ WORKLOADS = sorted(SINGLE) + ["batched512", "serving"]
 
 KERNELS = {"range": "k_range_check", "init": "k_greedy_topk+k_greedy_resolve",
            "layout": "k_transpose+k_build_w", "scan": "k_scan_pairs+k_scan_reduce",
-           "switch": "k_switch_ex"}
-KERNEL_SOURCES = {"k_switch_ex": "dgs_switch.hip", "k_scan_pairs+k_scan_reduce": "dgs_scan.hip",
+           "switch": "k_switch_v3"}
+KERNEL_SOURCES = {"k_switch_v3": "dgs_switch3.hip", "k_scan_pairs+k_scan_reduce": "dgs_scan.hip",
                   "k_batch_solve": "dgs_batch.hip"}
 
 

@@ -18,17 +18,19 @@
 // matches and no fences are needed.
 //
 // A workgroup's words: its best exchange (over its agents' lists, with the
-// job, partner and own job of that exchange), its most promising pending
-// agent (an agent whose list ran empty while its bound still promises a
-// positive gain) with that agent's job and benefit, and its top-2 "shares"
-// for each target of the round.  The share for target x is the best two of
+// job, partner and own job of that exchange), its two most promising
+// pending agents (agents whose list ran empty while their bound still
+// promises a positive gain) with their jobs and benefits, and its top-2
+// "shares" for each target of the round.  The share for target x is the best two of
 // g(r, x) over the workgroup's agents r.  Because g(r, x) = g(x, r), the
 // shares of all workgroups together are x's full re-evaluation: x's new list
 // holds the workgroup bests above the largest workgroup second, and that
 // second bounds everything else.  Targets are the two agents switched in
 // the previous round (their candidates all change) and up to kD pending
-// agents chosen in the previous round, largest bound first.  No agent is
-// ever re-evaluated by one workgroup alone.
+// agents chosen in the previous round, largest bound first; only the active
+// targets' words are exchanged.  No agent is ever re-evaluated by one
+// workgroup alone, and an owner rebuilds its targets' lists while the
+// round's loads are in flight.
 //
 // Decision (identical in every workgroup, computed from the words alone):
 // the best exchange among the workgroup bests and the targets' new bests.
@@ -48,18 +50,18 @@ namespace {
 
 using namespace dev;
 
-constexpr int kT = 256;                     // threads = agents per workgroup
-constexpr int kM = 8;                       // candidate list length
-constexpr int kD = 8;                       // pending agents re-evaluated per round
-constexpr int kTargets = 2 + kD;            // share targets per round
-constexpr int kWBest = 0, kWPay = 1, kWPend = 2, kWInfo = 3, kWShare = 4;
-constexpr int kW = kWShare + 2 * kTargets;  // words per workgroup per round
-constexpr int kVals = 2 + kTargets;         // per-thread values reduced at the top of a round
-constexpr int kMaxG = 256;                  // n <= 65535
+constexpr int kT = 256;                       // threads = agents per workgroup
+constexpr int kM = 8;                         // candidate list length
+constexpr int kD = 8;                         // pending agents re-evaluated per round
+constexpr int kTargets = 2 + kD;              // share target slots: i*, k, then the chosen pending agents
+// words of a workgroup in a round: best exchange, its payload, two pending agents and their
+// (benefit, job), then two share words per active target
+constexpr int kWBest = 0, kWPay = 1, kWPend = 2, kWInfo = 4, kWShare = 6;
+constexpr int kW = kWShare + 2 * kTargets;    // most words per workgroup per round
+constexpr int kMaxG = 256;                    // n <= 65535
 constexpr int kGatherPer = (kMaxG * kW + kT - 1) / kT;
-constexpr int kCand = kMaxG;
+constexpr int kCand = 2 * kMaxG;
 constexpr long long kSpinLimit = 1ll << 27;
-constexpr int kItems = 1 + 2 * kTargets;    // maxima over workgroups taken per round
 
 // ---- keys ------------------------------------------------------------------------------
 // List entry: gain^bias:32 | 0xFFFF-job:16 | partner agent:16.  Agent key:
@@ -78,51 +80,42 @@ __device__ __forceinline__ int kpartner(u64 k) { return (int)(k & 0xFFFFu); }
 __device__ __forceinline__ u64 hi48(u64 k) { return k & ~(u64)0xFFFF; }
 
 // ---- wave64 reductions on the DPP path -----------------------------------------------
-// quad_perm xor 1, quad_perm xor 2, reversal within 8 lanes, reversal within
-// 16 lanes: each pairs disjoint groups of lanes that already agree, so after
-// the four steps every lane of a 16-lane row holds the row's result; the
-// four rows are combined through readlane.  Call with all 64 lanes active.
+// 32-bit max in four steps (quad_perm xor 1, quad_perm xor 2, reversal within
+// 8 lanes, reversal within 16 lanes: each pairs disjoint groups of lanes that
+// already agree), each folded into one v_max_u32_dpp, then the four 16-lane
+// rows through readlane.  A 64-bit key takes two such passes: the high words,
+// then the low words of the lanes that hold the high maximum.  Call with all
+// 64 lanes active; the result is uniform.
 constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
 
 template <int CTRL>
-__device__ __forceinline__ u64 dpp64(u64 v) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, true);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, true);
-    return ((u64)hi << 32) | lo;
+__device__ __forceinline__ uint32_t dppu(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
 }
+__device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
-__device__ __forceinline__ u64 lane64(u64 v, int lane) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-    return ((u64)hi << 32) | lo;
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v) {
+    v = umax32(v, dppu<kDppXor1>(v));
+    v = umax32(v, dppu<kDppXor2>(v));
+    v = umax32(v, dppu<kDppHalfMirror>(v));
+    v = umax32(v, dppu<kDppMirror>(v));
+    const uint32_t a = umax32((uint32_t)__builtin_amdgcn_readlane((int)v, 0), (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
+    const uint32_t b = umax32((uint32_t)__builtin_amdgcn_readlane((int)v, 32), (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
+    return umax32(a, b);
 }
 
 __device__ __forceinline__ u64 wave_max(u64 v) {
-    v = umax64(v, dpp64<kDppXor1>(v));
-    v = umax64(v, dpp64<kDppXor2>(v));
-    v = umax64(v, dpp64<kDppHalfMirror>(v));
-    v = umax64(v, dpp64<kDppMirror>(v));
-    return umax64(umax64(lane64(v, 0), lane64(v, 16)), umax64(lane64(v, 32), lane64(v, 48)));
+    const uint32_t hi = wave_max32((uint32_t)(v >> 32));
+    const uint32_t lo = wave_max32((uint32_t)(v >> 32) == hi ? (uint32_t)v : 0u);
+    return ((u64)hi << 32) | lo;
 }
 
-template <int CTRL>
-__device__ __forceinline__ void top2_step(u64 &a1, u64 &a2) {
-    const u64 b1 = dpp64<CTRL>(a1), b2 = dpp64<CTRL>(a2);
-    top2_merge(a1, a2, b1, b2);
-}
-
-// Top-2 over the wave of keys that are unique apart from zeros.
+// Top-2 over the wave; every lane holds a1 >= a2, keys unique apart from zeros.
 __device__ __forceinline__ void wave_top2(u64 &a1, u64 &a2) {
-    top2_step<kDppXor1>(a1, a2);
-    top2_step<kDppXor2>(a1, a2);
-    top2_step<kDppHalfMirror>(a1, a2);
-    top2_step<kDppMirror>(a1, a2);
-    u64 r1 = lane64(a1, 0), r2 = lane64(a2, 0);
-    top2_merge(r1, r2, lane64(a1, 16), lane64(a2, 16));
-    top2_merge(r1, r2, lane64(a1, 32), lane64(a2, 32));
-    top2_merge(r1, r2, lane64(a1, 48), lane64(a2, 48));
-    a1 = r1;
-    a2 = r2;
+    const u64 m1 = wave_max(a1);
+    const u64 m2 = wave_max(a1 == m1 ? a2 : a1);
+    a1 = m1;
+    a2 = m2;
 }
 
 // ---- candidate lists (registers) --------------------------------------------------------
@@ -174,6 +167,7 @@ __device__ __forceinline__ void rank_select(const u64 *cand, int cnt, u64 *sel) 
     for (int e = threadIdx.x; e < cnt; e += kT) {
         const u64 me = hi48(cand[e]);
         int rank = 0;
+#pragma unroll 8
         for (int i = 0; i < cnt; ++i) rank += hi48(cand[i]) > me;
         if (rank <= kM) sel[rank] = cand[e];
     }
@@ -200,16 +194,17 @@ __device__ __forceinline__ void put_word(u64 *p, u64 w) {
 }
 
 __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
-    extern __shared__ __align__(16) u64 wl[];  // G * kW gathered words
-    __shared__ u64 vals[kVals][kT];
+    extern __shared__ __align__(16) u64 wl[];  // gathered words, G x (words of the round)
+    __shared__ u64 vals[2 + kTargets][kT];
     __shared__ u64 pay[kT];    // job, partner and own job of each agent's best exchange
     __shared__ u64 pinfo[kT];  // benefit and job of each agent
-    __shared__ u64 dec[kItems];
+    __shared__ u64 dec[1 + kTargets];
     __shared__ u64 cand[kCand];
     __shared__ u64 sel[kM + 1];
+    __shared__ u64 s_bnd;
     __shared__ int cand_n;
     __shared__ int s_err;
-    __shared__ int tg_agent[kTargets], tg_tau[kTargets];  // this round's targets
+    __shared__ int tg_agent[kTargets], tg_tau[kTargets];  // this round's target slots (-1: inactive)
     __shared__ int nx_agent[kD], nx_tau[kD], nx_d[kD];    // pending agents chosen this round
     __shared__ u64 nx_key[kD];
 
@@ -243,14 +238,17 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
     if (t == 0) s_err = 0;
     if (t < kTargets) tg_agent[t] = -1;
     if (t < kD) nx_agent[t] = -1;
-    u64 sh[kTargets];
+    u64 sh[kTargets];  // this thread's shares for the target slots
 #pragma unroll
     for (int i = 0; i < kTargets; ++i) sh[i] = 0;
+    uint32_t mask = 0;  // active target slots (uniform)
     int64_t S = 0, gsum = 0, refreshes = 0, stalls = 0;
     __syncthreads();
 
     for (uint32_t s = 0;; ++s) {
         const uint32_t tag = s & 0xFFu;
+        const int nt = __popc(mask);
+        const int kWa = kWShare + 2 * nt;  // words per workgroup this round
         u64 *buf = P.words + (size_t)(s & 1) * G * kW;
 
         // ---- this workgroup's words ------------------------------------------------------
@@ -270,20 +268,25 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             vals[0][t] = lk;
             vals[1][t] = pd;
 #pragma unroll
-            for (int i = 0; i < kTargets; ++i) vals[2 + i][t] = sh[i];
+            for (int i = 0; i < kTargets; ++i)
+                if (mask & (1u << i)) vals[2 + __popc(mask & ((1u << i) - 1))][t] = sh[i];
         }
         __syncthreads();
-        // wave w reduces value types w, w + 4, w + 8 and writes their words
-        for (int ty = wave; ty < kVals; ty += 4) {
-            if (ty < 2) {
-                u64 a = umax64(umax64(vals[ty][lane], vals[ty][lane + 64]),
-                               umax64(vals[ty][lane + 128], vals[ty][lane + 192]));
+        // wave w reduces value types w, w + 4, ...: 0 best (max), 1 pending (top-2), 2 + j shares
+        // (top-2).  Word w of a workgroup always sits at the same place and is always written by
+        // the same lane, every round (share words of inactive targets carry only the tag), so no
+        // older word with a matching tag can be left anywhere in the buffer.
+        for (int ty = wave; ty < 2 + kTargets; ty += 4) {
+            if (ty >= 2 + nt) {
+                if (lane < 2) put_word(&buf[(size_t)q * kW + kWShare + 2 * (ty - 2) + lane], (u64)tag);
+            } else if (ty == 0) {
+                u64 a = umax64(umax64(vals[0][lane], vals[0][lane + 64]),
+                               umax64(vals[0][lane + 128], vals[0][lane + 192]));
                 a = wave_max(a);
                 if (lane == 0) {
-                    u64 w1 = 0;
-                    if (a) w1 = (ty == 0 ? pay : pinfo)[kidx(a) - q * kT];
-                    put_word(&buf[(size_t)q * kW + (ty == 0 ? kWBest : kWPend)], a | tag);
-                    put_word(&buf[(size_t)q * kW + (ty == 0 ? kWPay : kWInfo)], (w1 & ~(u64)0xFF) | tag);
+                    const u64 w1 = a ? pay[kidx(a) - q * kT] : 0;
+                    put_word(&buf[(size_t)q * kW + kWBest], a | tag);
+                    put_word(&buf[(size_t)q * kW + kWPay], (w1 & ~(u64)0xFF) | tag);
                 }
             } else {
                 u64 a1 = vals[ty][lane], a2 = 0;
@@ -293,20 +296,31 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 wave_top2(a1, a2);
                 if (lane < 2) {
                     const u64 v = lane == 0 ? a1 : a2;
-                    const u64 w = v ? (hi48(v) | ((v & 0xFF) << 8)) : 0;  // local partner in bits 15..8
-                    put_word(&buf[(size_t)q * kW + kWShare + 2 * (ty - 2) + lane], w | tag);
+                    if (ty == 1) {
+                        const u64 info = v ? pinfo[kidx(v) - q * kT] : 0;
+                        put_word(&buf[(size_t)q * kW + kWPend + lane], v | tag);
+                        put_word(&buf[(size_t)q * kW + kWInfo + lane], (info & ~(u64)0xFF) | tag);
+                    } else {
+                        const u64 w = v ? (hi48(v) | ((v & 0xFF) << 8)) : 0;  // local partner in bits 15..8
+                        put_word(&buf[(size_t)q * kW + kWShare + 2 * (ty - 2) + lane], w | tag);
+                    }
                 }
             }
         }
 
         // ---- gather every workgroup's words ------------------------------------------------
+        // the first kWa words of each workgroup, packed as wl[q * kWa + w]
         {
-            const int NW = G * kW;
+            const int NW = G * kWa;
+            const uint32_t magic = (uint32_t)((0x100000000ull + (uint64_t)kWa - 1) / (uint64_t)kWa);
             u64 wv[kGatherPer];
+            int src[kGatherPer];
 #pragma unroll
             for (int i = 0; i < kGatherPer; ++i) {
                 const int x = t + i * kT;
-                wv[i] = x < NW ? __hip_atomic_load(&buf[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (u64)tag;
+                const int qq = (int)__umulhi((uint32_t)x, magic);  // x / kWa (exact for x < 2^16)
+                src[i] = qq * kW + (x - qq * kWa);
+                wv[i] = x < NW ? __hip_atomic_load(&buf[src[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (u64)tag;
             }
             long long spins = 0;
             for (;;) {
@@ -324,7 +338,7 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 for (int i = 0; i < kGatherPer; ++i) {
                     const int x = t + i * kT;
                     if (x < NW && (uint32_t)(wv[i] & 0xFFu) != tag)
-                        wv[i] = __hip_atomic_load(&buf[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        wv[i] = __hip_atomic_load(&buf[src[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
 #pragma unroll
@@ -336,34 +350,28 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         __syncthreads();
         if (s_err) break;
 
-        // ---- maxima over workgroups and the pending agents to re-evaluate ----------------
-        // item 0: best exchange; 1 + T: best share of target T; 1 + kTargets + T:
-        // second share of target T (needed by the target's owner only).  Each
-        // maximum carries the index of the workgroup it came from in bits 7..0.
-        for (int it = wave; it < kItems; it += 4) {
-            int widx;
-            if (it == 0) {
-                widx = kWBest;
-            } else if (it <= kTargets) {
-                widx = kWShare + 2 * (it - 1);
-            } else {
-                const int T = it - 1 - kTargets;
-                const int x = tg_agent[T];
-                if (x < 0 || x / kT != q) continue;
-                widx = kWShare + 2 * T + 1;
-            }
+        // ---- maxima over workgroups, and the pending agents to re-evaluate ----------------
+        // item 0: best exchange; item 1 + j: best share of the j-th active target.  Each
+        // maximum carries the index of its workgroup in bits 7..0.
+        for (int it = wave; it <= nt; it += 4) {
+            const int widx = it == 0 ? kWBest : kWShare + 2 * (it - 1);
             u64 m = 0;
-            for (int qq = lane; qq < G; qq += 64) m = umax64(m, (wl[qq * kW + widx] & ~(u64)0xFF) | (u64)qq);
+            for (int qq = lane; qq < G; qq += 64) m = umax64(m, (wl[qq * kWa + widx] & ~(u64)0xFF) | (u64)qq);
             m = wave_max(m);
             if (lane == 0) dec[it] = m;
         }
-        if (t < G) {
-            const u64 me = hi48(wl[t * kW + kWPend]);
+        // the kD largest of the 2G published pending keys (unique), by rank
+        for (int e = t; e < 2 * G; e += kT) {
+            const u64 me = hi48(wl[(e >> 1) * kWa + kWPend + (e & 1)]);
             if (me) {
                 int rank = 0;
-                for (int qq = 0; qq < G; ++qq) rank += hi48(wl[qq * kW + kWPend]) > me;
+#pragma unroll 4
+                for (int qq = 0; qq < G; ++qq) {
+                    rank += hi48(wl[qq * kWa + kWPend]) > me;
+                    rank += hi48(wl[qq * kWa + kWPend + 1]) > me;
+                }
                 if (rank < kD) {
-                    const u64 info = wl[t * kW + kWInfo];
+                    const u64 info = wl[(e >> 1) * kWa + kWInfo + (e & 1)];
                     nx_key[rank] = me;
                     nx_agent[rank] = kidx(me);
                     nx_tau[rank] = (int)((info >> 16) & 0xFFFFu);
@@ -373,58 +381,33 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         }
         __syncthreads();
 
-        // ---- the best exchange --------------------------------------------------------------
+        // ---- decide ---------------------------------------------------------------------------
         u64 best = 0;
         int bj = -1, bk = -1, bj0 = -1;  // job, partner and own job of the best exchange
         {
             const u64 mb = dec[0];
             if (hi48(mb)) {
                 const int a = kidx(mb);
-                const u64 pw = wl[(a / kT) * kW + kWPay];
+                const u64 pw = wl[(a / kT) * kWa + kWPay];
                 best = hi48(mb);
                 bj = (int)((pw >> 48) & 0xFFFFu);
                 bk = (int)((pw >> 32) & 0xFFFFu);
                 bj0 = (int)((pw >> 16) & 0xFFFFu);
             }
         }
-        for (int T = 0; T < kTargets; ++T) {
-            const int x = tg_agent[T];
-            const u64 m = dec[1 + T];
-            if (x < 0 || hi48(m) == 0) continue;
-            const u64 c = ak_key(kgain(m), x);
+#pragma unroll
+        for (int i = 0; i < kTargets; ++i) {
+            if (!(mask & (1u << i))) continue;
+            const u64 m = dec[1 + __popc(mask & ((1u << i) - 1))];
+            if (hi48(m) == 0) continue;
+            const u64 c = ak_key(kgain(m), tg_agent[i]);
             if (c > best) {
                 best = c;
                 bj = kidx(m);
                 bk = (int)(m & 0xFF) * kT + (int)((m >> 8) & 0xFF);
-                bj0 = tg_tau[T];
+                bj0 = tg_tau[i];
             }
         }
-
-        // ---- owners rebuild the lists of this round's targets ------------------------------
-        for (int T = 0; T < kTargets; ++T) {
-            const int x = tg_agent[T];
-            if (x < 0 || x / kT != q) continue;  // uniform across the workgroup
-            const u64 bnd = hi48(dec[1 + kTargets + T]);
-            if (t == 0) cand_n = 0;
-            if (t <= kM) sel[t] = 0;
-            __syncthreads();
-            if (t < G) {
-                const u64 w = wl[t * kW + kWShare + 2 * T];
-                if (hi48(w) > bnd) cand[atomicAdd(&cand_n, 1)] = hi48(w) | (u64)(t * kT + (int)((w >> 8) & 0xFF));
-            }
-            __syncthreads();
-            rank_select(cand, cand_n, sel);
-            __syncthreads();
-            if (r == x) {
-#pragma unroll
-                for (int i = 0; i < kM; ++i) L[i] = sel[i];
-                B = umax64(bnd, hi48(sel[kM]));
-                inflight = false;
-            }
-            __syncthreads();
-        }
-
-        // ---- decide ---------------------------------------------------------------------------
         if (P.max_switches >= 0 && S >= P.max_switches) break;
         const bool stall = nx_agent[0] >= 0 && nx_key[0] > best;  // pending bounds have gain > 0
         if (!stall && (best == 0 || kgain(best) <= 0)) break;
@@ -444,7 +427,7 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             dk = P.A[(int64_t)k * nn + j0];    // a[k][j0]
         }
 
-        // ---- loads of this round: the switch's changed candidates and the re-evaluations --
+        // ---- loads of the round: the switch's changed candidates and the re-evaluations ---
         int a1 = 0, a2 = 0, w1 = 0, w2 = 0;
         int tr2 = tr, dr2 = dr;  // job and benefit after this round's switch
         if (mine && !stall) {
@@ -472,7 +455,42 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             }
         }
 
-        // ---- apply the switch to this workgroup's agents; shares for next round ----------
+        // ---- owners rebuild the lists of this round's targets (while the loads are in flight)
+#pragma unroll
+        for (int i = 0; i < kTargets; ++i) {
+            if (!(mask & (1u << i))) continue;
+            const int x = tg_agent[i];
+            if (x / kT != q || x == is || x == k) continue;  // uniform across the workgroup
+            const int sw = kWShare + 2 * __popc(mask & ((1u << i) - 1));
+            if (wave == 0) {
+                u64 m = 0;
+                for (int qq = lane; qq < G; qq += 64) m = umax64(m, hi48(wl[qq * kWa + sw + 1]));
+                m = wave_max(m);
+                if (lane == 0) {
+                    s_bnd = m;
+                    cand_n = 0;
+                }
+                if (lane <= kM) sel[lane] = 0;
+            }
+            __syncthreads();
+            const u64 bnd = s_bnd;
+            for (int qq = t; qq < G; qq += kT) {
+                const u64 w = wl[qq * kWa + sw];
+                if (hi48(w) > bnd) cand[atomicAdd(&cand_n, 1)] = hi48(w) | (u64)(qq * kT + (int)((w >> 8) & 0xFF));
+            }
+            __syncthreads();
+            rank_select(cand, cand_n, sel);
+            __syncthreads();
+            if (r == x) {
+#pragma unroll
+                for (int e = 0; e < kM; ++e) L[e] = sel[e];
+                B = umax64(bnd, hi48(sel[kM]));
+                inflight = false;
+            }
+            __syncthreads();
+        }
+
+        // ---- apply the switch to this workgroup's agents; shares for the next round -------
         u64 nsh[kTargets];
 #pragma unroll
         for (int i = 0; i < kTargets; ++i) nsh[i] = 0;
@@ -507,48 +525,42 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         } else {
             ++stalls;
         }
+        uint32_t nmask = stall ? 0u : 3u;
 #pragma unroll
         for (int dd = 0; dd < kD; ++dd) {
             const int x = nx_agent[dd];
-            if (mine && x >= 0 && x != is && x != k && r != x)
-                nsh[2 + dd] = le_key((ra[dd] + rb[dd]) - (dr + nx_d[dd]), tr, t);  // g(r, x)
-            if (mine && x == r && r != is && r != k) inflight = true;
+            const bool live = x >= 0 && x != is && x != k;
+            if (live) nmask |= 1u << (2 + dd);
+            if (mine && live && r != x) nsh[2 + dd] = le_key((ra[dd] + rb[dd]) - (dr + nx_d[dd]), tr, t);  // g(r, x)
+            if (mine && live && r == x) inflight = true;
         }
-        int nref = 0;
-#pragma unroll
-        for (int dd = 0; dd < kD; ++dd) {
-            const int x = nx_agent[dd];
-            nref += (x >= 0 && x != is && x != k) ? 1 : 0;
-        }
-        refreshes += nref;
-        __syncthreads();  // every thread has read this round's targets and pending choices
+        refreshes += __popc(nmask >> 2);
+        __syncthreads();  // every thread has read this round's target slots and pending choices
         if (t < kTargets) {
             if (t == 0) {
-                tg_agent[0] = is;
+                tg_agent[0] = stall ? -1 : is;
                 tg_tau[0] = js;
             } else if (t == 1) {
-                tg_agent[1] = k;
+                tg_agent[1] = stall ? -1 : k;
                 tg_tau[1] = j0;
             } else {
                 const int dd = t - 2;
-                const int x = nx_agent[dd];
-                tg_agent[t] = (x >= 0 && x != is && x != k) ? x : -1;
+                tg_agent[t] = (nmask >> t) & 1u ? nx_agent[dd] : -1;
                 tg_tau[t] = nx_tau[dd];
                 nx_agent[dd] = -1;
             }
         }
+        mask = nmask;
 #pragma unroll
         for (int i = 0; i < kTargets; ++i) sh[i] = nsh[i];
     }
 
     if (mine) P.tau[r] = tr;
-    if (t == 0) {
-        if (q == 0) {
-            P.stats[0] = S;
-            P.stats[1] = gsum;
-            P.stats[3] = refreshes;
-            P.stats[4] = stalls;
-        }
+    if (t == 0 && q == 0) {
+        P.stats[0] = S;
+        P.stats[1] = gsum;
+        P.stats[3] = refreshes;
+        P.stats[4] = stalls;
     }
 }
 
