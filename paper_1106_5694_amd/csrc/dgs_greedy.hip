@@ -152,7 +152,25 @@ __global__ __launch_bounds__(256) void k_greedy_resolve(ResolveParams P) {
     uint32_t *tk = (uint32_t *)(smem + (size_t)P.rows * P.chunks * 64 * 8);  // n / 32 words
     const int words = (P.n + 31) >> 5;
     const int total = P.rows * P.chunks * 64;
-    for (int i = threadIdx.x; i < total; i += blockDim.x) L[i] = P.lists[i];
+    // stage the lists: 16-byte loads, eight in flight per thread (total is a multiple of 64)
+    {
+        const int4 *src = (const int4 *)P.lists;
+        int4 *dst = (int4 *)L;
+        const int total4 = total / 2;
+        for (int base = threadIdx.x; base < total4; base += 8 * blockDim.x) {
+            int4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * blockDim.x;
+                if (i < total4) v[u] = src[i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * blockDim.x;
+                if (i < total4) dst[i] = v[u];
+            }
+        }
+    }
     for (int i = threadIdx.x; i < words; i += blockDim.x) tk[i] = P.taken[i];
     __syncthreads();
     if (threadIdx.x < 64) {

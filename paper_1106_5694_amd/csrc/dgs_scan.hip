@@ -22,7 +22,7 @@ namespace {
 using namespace dev;
 
 constexpr int kTile = 64;
-constexpr int kScanBlock = 256;
+constexpr int kScanBlock = 512;  // 8 threads per tile row
 constexpr int kPad = kTile + 1;
 constexpr int kListLen = kScanListLen;
 
@@ -49,7 +49,14 @@ struct ScanParams {
     int nb;
 };
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_pairs(ScanParams P) {
+// One workgroup of BLOCK threads per tile pair: BLOCK / 64 threads per tile
+// row, each scoring 64 / (BLOCK / 64) partners on each side; interior pairs
+// (no bounds, no diagonal) take an unrolled path.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
+    constexpr int Q = BLOCK / 64;  // threads per tile row
+    constexpr int E = kTile / Q;   // partners per thread
+    constexpr int LD = (kTile * kTile / 4) / BLOCK;  // int4 loads per thread per tile
     __shared__ int32_t tA[kTile][kPad];  // tA[i][k] = W[I*T + i][K*T + k]
     __shared__ int32_t tB[kTile][kPad];  // tB[k][i] = W[K*T + k][I*T + i]
     __shared__ int32_t dI[kTile], dK[kTile], jI[kTile], jK[kTile];
@@ -58,20 +65,19 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_pairs(ScanParams P) {
     const int n = P.n;
     const int i0 = I * kTile, k0 = K * kTile;
     const int t = threadIdx.x;
-    // load both tiles: 64 rows x 16 int4 each; thread t loads 4 int4 per tile
     const bool full = (n % 4 == 0) && i0 + kTile <= n && k0 + kTile <= n;
     if (full) {
-        int4 va[4], vb[4];
+        int4 va[LD], vb[LD];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = t + u * kScanBlock;  // 0..1023
+        for (int u = 0; u < LD; ++u) {
+            const int e = t + u * BLOCK;
             const int r = e >> 4, c4 = (e & 15) * 4;
             va[u] = *(const int4 *)(P.W + (int64_t)(i0 + r) * n + k0 + c4);
             vb[u] = *(const int4 *)(P.W + (int64_t)(k0 + r) * n + i0 + c4);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = t + u * kScanBlock;
+        for (int u = 0; u < LD; ++u) {
+            const int e = t + u * BLOCK;
             const int r = e >> 4, c4 = (e & 15) * 4;
             tA[r][c4] = va[u].x;
             tA[r][c4 + 1] = va[u].y;
@@ -83,7 +89,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_pairs(ScanParams P) {
             tB[r][c4 + 3] = vb[u].w;
         }
     } else {
-        for (int e = t; e < kTile * kTile; e += kScanBlock) {
+        for (int e = t; e < kTile * kTile; e += BLOCK) {
             const int r = e >> 6, c = e & 63;
             tA[r][c] = (i0 + r < n && k0 + c < n) ? P.W[(int64_t)(i0 + r) * n + k0 + c] : 0;
             tB[r][c] = (k0 + r < n && i0 + c < n) ? P.W[(int64_t)(k0 + r) * n + i0 + c] : 0;
@@ -99,51 +105,49 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_pairs(ScanParams P) {
     }
     __syncthreads();
 
-    // rows of block I against partners in K: thread t -> row t/4, partners (t%4)*16 ..
-    {
-        const int i = t >> 2, q = t & 3;
-        u64 b1 = 0, b2 = 0;
-        if (i0 + i < n) {
-            const int di = dI[i];
-#pragma unroll 4
-            for (int e = 0; e < 16; ++e) {
-                const int k = q * 16 + e;
-                if (k0 + k >= n || (I == K && k == i)) continue;
-                const int g = (tA[i][k] + tB[k][i]) - (di + dK[k]);
-                top2_push(b1, b2, mk_key(g, jK[k]));
+    const int rt = t / Q, q = t % Q;
+    u64 a1 = 0, a2 = 0, c1 = 0, c2 = 0;  // row rt of I against K; row rt of K against I
+    if (I != K && i0 + kTile <= n && k0 + kTile <= n) {
+        const int di = dI[rt], dk = dK[rt];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int c = q * E + e;
+            top2_push(a1, a2, mk_key((tA[rt][c] + tB[c][rt]) - (di + dK[c]), jK[c]));
+            top2_push(c1, c2, mk_key((tA[c][rt] + tB[rt][c]) - (dI[c] + dk), jI[c]));
+        }
+    } else {
+        if (i0 + rt < n) {
+            const int di = dI[rt];
+            for (int e = 0; e < E; ++e) {
+                const int k = q * E + e;
+                if (k0 + k >= n || (I == K && k == rt)) continue;
+                top2_push(a1, a2, mk_key((tA[rt][k] + tB[k][rt]) - (di + dK[k]), jK[k]));
             }
         }
-        // merge the 4 quarter-threads of row i (adjacent lanes)
-#pragma unroll
-        for (int m = 1; m <= 2; m <<= 1) top2_merge(b1, b2, shfl_xor64(b1, m), shfl_xor64(b2, m));
-        if (q == 0 && i0 + i < n) {
-            u64 *o = P.part + ((size_t)(i0 + i) * P.nb + K) * 2;
-            o[0] = b1;
-            o[1] = b2;
+        if (I != K && k0 + rt < n) {
+            const int dk = dK[rt];
+            for (int e = 0; e < E; ++e) {
+                const int i = q * E + e;
+                if (i0 + i >= n) continue;
+                top2_push(c1, c2, mk_key((tA[i][rt] + tB[rt][i]) - (dI[i] + dk), jI[i]));
+            }
         }
     }
-    if (I == K) return;
-    // rows of block K against partners in I
-    {
-        const int k = t >> 2, q = t & 3;
-        u64 b1 = 0, b2 = 0;
-        if (k0 + k < n) {
-            const int dk = dK[k];
-#pragma unroll 4
-            for (int e = 0; e < 16; ++e) {
-                const int i = q * 16 + e;
-                if (i0 + i >= n) continue;
-                const int g = (tA[i][k] + tB[k][i]) - (dI[i] + dk);
-                top2_push(b1, b2, mk_key(g, jI[i]));
-            }
-        }
+    // merge the Q threads of each row (adjacent lanes)
 #pragma unroll
-        for (int m = 1; m <= 2; m <<= 1) top2_merge(b1, b2, shfl_xor64(b1, m), shfl_xor64(b2, m));
-        if (q == 0 && k0 + k < n) {
-            u64 *o = P.part + ((size_t)(k0 + k) * P.nb + I) * 2;
-            o[0] = b1;
-            o[1] = b2;
-        }
+    for (int m = 1; m < Q; m <<= 1) {
+        top2_merge(a1, a2, shfl_xor64(a1, m), shfl_xor64(a2, m));
+        top2_merge(c1, c2, shfl_xor64(c1, m), shfl_xor64(c2, m));
+    }
+    if (q == 0 && i0 + rt < n) {
+        u64 *o = P.part + ((size_t)(i0 + rt) * P.nb + K) * 2;
+        o[0] = a1;
+        o[1] = a2;
+    }
+    if (q == 0 && I != K && k0 + rt < n) {
+        u64 *o = P.part + ((size_t)(k0 + rt) * P.nb + I) * 2;
+        o[0] = c1;
+        o[1] = c2;
     }
 }
 
@@ -155,12 +159,25 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_pairs(ScanParams P) {
 __global__ __launch_bounds__(256) void k_scan_reduce(const u64 *__restrict__ part, int n, int nb,
                                                       const int32_t *__restrict__ sigma, u64 *bk, u64 *bb,
                                                       int32_t *bc, u64 *lists) {
+    constexpr int kPer = 8;  // block bests held per lane: nb <= 512 (n <= 32768) stays in registers
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= n) return;
     const u64 *p = part + (size_t)r * nb * 2;
     u64 bnd = 0;
-    for (int x = lane; x < nb; x += 64) bnd = umax64(bnd, p[2 * x + 1]);
+    u64 best[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) best[m] = 0;
+    const bool regs = nb <= 64 * kPer;
+    for (int x = lane; x < nb; x += 64) {
+        const u64 b1 = p[2 * x], b2 = p[2 * x + 1];
+        bnd = umax64(bnd, b2);
+        if (regs) {
+#pragma unroll
+            for (int m = 0; m < kPer; ++m)
+                if (x == lane + 64 * m) best[m] = b1;
+        }
+    }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) bnd = umax64(bnd, shfl_xor64(bnd, m));
     // up to kListLen + 1 rounds of "largest block best above the bound"
@@ -169,9 +186,15 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const u64 *__restrict__ par
     u64 first = 0;
     for (int round = 0; round <= kListLen; ++round) {
         u64 m1 = 0;
-        for (int x = lane; x < nb; x += 64) {
-            const u64 k = p[2 * x];
-            if (k > bnd && k < taken_max) m1 = umax64(m1, k);
+        if (regs) {
+#pragma unroll
+            for (int m = 0; m < kPer; ++m)
+                if (best[m] > bnd && best[m] < taken_max) m1 = umax64(m1, best[m]);
+        } else {
+            for (int x = lane; x < nb; x += 64) {
+                const u64 k = p[2 * x];
+                if (k > bnd && k < taken_max) m1 = umax64(m1, k);
+            }
         }
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) m1 = umax64(m1, shfl_xor64(m1, m));
@@ -203,7 +226,7 @@ hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s) {
     const int nb = (I.n + kTile - 1) / kTile;
     const long long pairs = (long long)nb * (nb + 1) / 2;
     ScanParams P{I.W, I.tau, I.d, (u64 *)scratch, I.n, nb};
-    hipLaunchKernelGGL(k_scan_pairs, dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    hipLaunchKernelGGL(k_scan_pairs_b<kScanBlock>, dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
                        nb, I.sigma, I.bk, I.bb, I.bc, I.lists);
     return hipGetLastError();
