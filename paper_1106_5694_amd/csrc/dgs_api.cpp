@@ -49,7 +49,6 @@ struct Context {
     std::string init_error;
     // Cooperative switch loops need every workgroup resident; one at a time.
     std::mutex loop_mu;
-    bool loop_v2 = false;  // DGS_SWITCH_LOOP=v2: the switching loop with owner re-evaluations
 };
 
 Context g_ctx;
@@ -64,8 +63,6 @@ dgs_status ensure_context() {
             return;
         }
         if (hipGetDevice(&g_ctx.device) != hipSuccess) g_ctx.device = 0;
-        const char *loop = getenv("DGS_SWITCH_LOOP");
-        g_ctx.loop_v2 = loop && std::string(loop) == "v2";
         g_ctx.loop_grid = loop_grid_size(g_ctx.device);
         if (g_ctx.loop_grid < 1) {
             g_ctx.init_status = DGS_E_DEVICE;
@@ -108,7 +105,7 @@ std::multimap<int32_t, Workspace *> g_ws_free;
 // 256-byte boundary; vec_layout() is the single source of the offsets used
 // both to size the allocation and to carve it.
 struct VecLayout {
-    size_t tau, sigma, d, bc, bk, bb, lists, recs, barrier, stats, flags, words, replica, greedy, scan, total;
+    size_t tau, sigma, d, bc, bk, bb, lists, recs, barrier, stats, flags, words, greedy, scan, total;
 };
 
 VecLayout vec_layout(int32_t n, int grid) {
@@ -131,8 +128,7 @@ VecLayout vec_layout(int32_t n, int grid) {
     L.stats = take(8 * sizeof(int64_t));
     L.flags = take(4 * sizeof(int32_t));
     const bool ex = n >= 2 && n <= kSwitchExMaxN;
-    L.words = take(ex ? std::max(switch_ex_word_bytes(n), switch_v3_word_bytes(n)) : 0);
-    L.replica = take(ex ? switch_ex_replica_bytes(n) : 0);
+    L.words = take(ex ? switch_v3_word_bytes(n) : 0);
     L.greedy = take(greedy_scratch_bytes(n));
     L.scan = take(scan_pairs_scratch_bytes(n));
     L.total = off;
@@ -220,7 +216,6 @@ Instance carve(Workspace *w, const int32_t *A, int32_t n, int grid) {
     I.stats = (int64_t *)(p + L.stats);
     I.flags = (int32_t *)(p + L.flags);
     I.words = p + L.words;
-    I.replica = p + L.replica;
     I.greedy = p + L.greedy;
     I.scan = p + L.scan;
     return I;
@@ -321,13 +316,8 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         if (c.coop) lk.lock();
         if (n >= 2 && n <= kSwitchExMaxN) {
             // stale round tags must not match rounds 0 and 1
-            if (g_ctx.loop_v2) {
-                DGS_HIP(hipMemsetAsync(I.words, 0xFF, switch_ex_word_bytes(n), s));
-                DGS_HIP(launch_switch_ex(I, c.max_switches, I.words, I.replica, I.flags + 2, c.coop, s));
-            } else {
-                DGS_HIP(hipMemsetAsync(I.words, 0xFF, switch_v3_word_bytes(n), s));
-                DGS_HIP(launch_switch_v3(I, c.max_switches, I.words, I.flags + 2, c.coop, s));
-            }
+            DGS_HIP(hipMemsetAsync(I.words, 0xFF, switch_v3_word_bytes(n), s));
+            DGS_HIP(launch_switch_v3(I, c.max_switches, I.words, I.flags + 2, c.coop, s));
         } else if (n > kSwitchExMaxN) {
             DGS_HIP(launch_switch_loop(I, c.max_switches, grid, s));
         }
@@ -586,7 +576,7 @@ dgs_status check_common(const int32_t *benefit, int32_t n, const void *out) {
 int switch_loop_grid(int n) {
     if (n < 2) return 0;
     if (n > kSwitchExMaxN) return g_ctx.loop_grid;
-    return g_ctx.loop_v2 ? switch_ex_grid(n) : switch_v3_grid(n);
+    return switch_v3_grid(n);
 }
 
 int device_cus() {

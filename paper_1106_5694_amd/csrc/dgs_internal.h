@@ -43,7 +43,6 @@ struct Instance {
     int64_t *stats = nullptr;    // [0] switches, [1] gain sum, [2] f0, [3] re-evaluations, [4] stalls
     int32_t *flags = nullptr;    // [0] range error, [1] permutation error, [2] wait timed out
     void *words = nullptr;       // exchange words of the switching loop
-    void *replica = nullptr;     // private replicas of the switching loop (large n)
     void *greedy = nullptr;      // scratch of the greedy start
     void *scan = nullptr;        // scratch of the difference evaluation (per-block top-2)
     u64 *lists = nullptr;        // [n][kScanListLen] initial candidate lists (keys, 0 = empty)
@@ -86,18 +85,8 @@ hipError_t launch_scan_rows(const Instance &I, hipStream_t s);
 size_t scan_pairs_scratch_bytes(int n);
 hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s);
 hipError_t launch_switch_loop(const Instance &I, int64_t max_switches, int grid, hipStream_t s);
-// Switching loop with fence-free exchange (dgs_switch.hip), for 2 <= n <= kSwitchExMaxN.
+// Largest n of the switching loop with cooperative re-evaluation (16-bit agent and job fields).
 constexpr int kSwitchExMaxN = 65535;
-int switch_ex_grid(int n);
-size_t switch_ex_word_bytes(int n);
-bool switch_ex_lds_replica(int n);
-size_t switch_ex_replica_bytes(int n);
-// coop: cooperative launch (co-residency guaranteed by the runtime); else a
-// plain launch whose caller guarantees that its workgroups fit beside the
-// other persistent work on the device.
-hipError_t launch_switch_ex(const Instance &I, int64_t max_switches, void *words, void *replica, int32_t *err,
-                            bool coop, hipStream_t s);
-
 // Switching loop with cooperative re-evaluation (dgs_switch3.hip), for 2 <= n <= kSwitchExMaxN:
 // grid of switch_v3_grid(n) workgroups, exchange words of switch_v3_word_bytes(n) (set to 0xFF first).
 int switch_v3_grid(int n);

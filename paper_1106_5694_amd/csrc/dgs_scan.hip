@@ -169,14 +169,17 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const u64 *__restrict__ par
 #pragma unroll
     for (int m = 0; m < kPer; ++m) best[m] = 0;
     const bool regs = nb <= 64 * kPer;
-    for (int x = lane; x < nb; x += 64) {
-        const u64 b1 = p[2 * x], b2 = p[2 * x + 1];
-        bnd = umax64(bnd, b2);
-        if (regs) {
+    if (regs) {
 #pragma unroll
-            for (int m = 0; m < kPer; ++m)
-                if (x == lane + 64 * m) best[m] = b1;
+        for (int m = 0; m < kPer; ++m) {
+            const int x = lane + 64 * m;
+            if (x < nb) {
+                best[m] = p[2 * x];
+                bnd = umax64(bnd, p[2 * x + 1]);
+            }
         }
+    } else {
+        for (int x = lane; x < nb; x += 64) bnd = umax64(bnd, p[2 * x + 1]);
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) bnd = umax64(bnd, shfl_xor64(bnd, m));
