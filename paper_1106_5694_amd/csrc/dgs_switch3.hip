@@ -60,7 +60,6 @@ constexpr int kWBest = 0, kWPay = 1, kWPend = 2, kWInfo = 4, kWShare = 6;
 constexpr int kW = kWShare + 2 * kTargets;    // most words per workgroup per round
 constexpr int kMaxG = 256;                    // n <= 65535
 constexpr int kGatherPer = (kMaxG * kW + kT - 1) / kT;
-constexpr int kCand = 2 * kMaxG;
 constexpr long long kSpinLimit = 1ll << 27;
 
 // ---- keys ------------------------------------------------------------------------------
@@ -161,17 +160,21 @@ __device__ __forceinline__ void list_drop_jobs(u64 (&L)[kM], int j1, int j2) {
     }
 }
 
-// Entries of rank 0..kM (largest first) among cand[0..cnt) go to sel[rank];
-// sel[0..kM] must be zero beforehand.  Upper 48 bits are unique.
-__device__ __forceinline__ void rank_select(const u64 *cand, int cnt, u64 *sel) {
-    for (int e = threadIdx.x; e < cnt; e += kT) {
-        const u64 me = hi48(cand[e]);
-        int rank = 0;
-#pragma unroll 8
-        for (int i = 0; i < cnt; ++i) rank += hi48(cand[i]) > me;
-        if (rank <= kM) sel[rank] = cand[e];
+// Slot of the nth active target (nth < popcount(mask)); mask is uniform.
+__device__ __forceinline__ int nth_slot(uint32_t mask, int nth) {
+    int slot = 0;
+#pragma unroll
+    for (int i = 0; i < kTargets; ++i) {
+        if (mask & (1u << i)) {
+            if (nth == 0) slot = i;
+            --nth;
+        }
     }
+    return slot;
 }
+
+// Number of lanes below this one whose bit is set in a wave ballot.
+__device__ __forceinline__ int lanes_below(u64 bal, int lane) { return __popcll(bal & ((1ull << lane) - 1)); }
 
 struct V3Params {
     const int32_t *A;
@@ -198,15 +201,13 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
     __shared__ u64 vals[2 + kTargets][kT];
     __shared__ u64 pay[kT];    // job, partner and own job of each agent's best exchange
     __shared__ u64 pinfo[kT];  // benefit and job of each agent
-    __shared__ u64 dec[1 + kTargets];
-    __shared__ u64 cand[kCand];
-    __shared__ u64 sel[kM + 1];
-    __shared__ u64 s_bnd;
-    __shared__ int cand_n;
+    __shared__ u64 dec_key;    // largest decision key of the round; item number in the low byte
+    __shared__ u64 dec_pay[1 + kTargets];  // per item: job << 48 | partner << 32 | own job << 16
+    __shared__ int4 nx[kD];                // pending agents chosen this round: agent (-1: none), job, benefit
+    __shared__ u64 nx_key0;                // key of the first chosen pending agent (0: none)
+    __shared__ u64 rcand[kT / 64][kMaxG];  // per wave: candidates of a list being rebuilt
+    __shared__ u64 rsel[kT / 64][kM + 1];
     __shared__ int s_err;
-    __shared__ int tg_agent[kTargets], tg_tau[kTargets];  // this round's target slots (-1: inactive)
-    __shared__ int nx_agent[kD], nx_tau[kD], nx_d[kD];    // pending agents chosen this round
-    __shared__ u64 nx_key[kD];
 
     if (P.flags[0]) return;  // same decision in every workgroup
     const int G = gridDim.x, q = blockIdx.x, t = threadIdx.x, n = P.n;
@@ -236,8 +237,13 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         B = b ? hi48(le_key(key_gain(b), key_index(b), 0)) : 0;
     }
     if (t == 0) s_err = 0;
-    if (t < kTargets) tg_agent[t] = -1;
-    if (t < kD) nx_agent[t] = -1;
+    // This round's target slots (uniform): agent (-1: inactive) and its job.
+    int tg_agent[kTargets], tg_tau[kTargets];
+#pragma unroll
+    for (int i = 0; i < kTargets; ++i) {
+        tg_agent[i] = -1;
+        tg_tau[i] = 0;
+    }
     u64 sh[kTargets];  // this thread's shares for the target slots
 #pragma unroll
     for (int i = 0; i < kTargets; ++i) sh[i] = 0;
@@ -272,6 +278,12 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 if (mask & (1u << i)) vals[2 + __popc(mask & ((1u << i) - 1))][t] = sh[i];
         }
         __syncthreads();
+        // every thread has read the previous round's decision and pending choice
+        if (t == 0) {
+            dec_key = 0;
+            nx_key0 = 0;
+        }
+        if (t < kD) nx[t] = make_int4(-1, 0, 0, 0);
         // wave w reduces value types w, w + 4, ...: 0 best (max), 1 pending (top-2), 2 + j shares
         // (top-2).  Word w of a workgroup always sits at the same place and is always written by
         // the same lane, every round (share words of inactive targets carry only the tag), so no
@@ -350,69 +362,81 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         __syncthreads();
         if (s_err) break;
 
-        // ---- maxima over workgroups, and the pending agents to re-evaluate ----------------
-        // item 0: best exchange; item 1 + j: best share of the j-th active target.  Each
-        // maximum carries the index of its workgroup in bits 7..0.
-        for (int it = wave; it <= nt; it += 4) {
-            const int widx = it == 0 ? kWBest : kWShare + 2 * (it - 1);
-            u64 m = 0;
-            for (int qq = lane; qq < G; qq += 64) m = umax64(m, (wl[qq * kWa + widx] & ~(u64)0xFF) | (u64)qq);
-            m = wave_max(m);
-            if (lane == 0) dec[it] = m;
-        }
-        // the kD largest of the 2G published pending keys (unique), by rank
-        for (int e = t; e < 2 * G; e += kT) {
-            const u64 me = hi48(wl[(e >> 1) * kWa + kWPend + (e & 1)]);
-            if (me) {
-                int rank = 0;
-#pragma unroll 4
-                for (int qq = 0; qq < G; ++qq) {
-                    rank += hi48(wl[qq * kWa + kWPend]) > me;
-                    rank += hi48(wl[qq * kWa + kWPend + 1]) > me;
+        // ---- maxima over workgroups (waves 2-3), pending agents to re-evaluate (waves 0-1) ----
+        if (wave >= 2) {
+            // item 0: best exchange; item 1 + j: best share of the j-th active target.  Each
+            // wave turns its items into decision candidates: a key (gain, agent) with the item
+            // number below it, and the exchange's job, partner and own job.
+            for (int it = wave - 2; it <= nt; it += 2) {
+                const int widx = it == 0 ? kWBest : kWShare + 2 * (it - 1);
+                u64 m = 0;
+                for (int qq = lane; qq < G; qq += 64) m = umax64(m, (wl[qq * kWa + widx] & ~(u64)0xFF) | (u64)qq);
+                m = wave_max(m);
+                if (hi48(m) != 0 && lane == 0) {
+                    u64 key, pw;
+                    if (it == 0) {
+                        key = hi48(m);
+                        pw = wl[(kidx(m) / kT) * kWa + kWPay] & ~(u64)0xFFFF;
+                    } else {
+                        const int i = nth_slot(mask, it - 1);
+                        key = ak_key(kgain(m), tg_agent[i]);
+                        const int partner = (int)(m & 0xFF) * kT + (int)((m >> 8) & 0xFF);
+                        pw = ((u64)(uint32_t)kidx(m) << 48) | ((u64)(uint32_t)partner << 32) |
+                             ((u64)(uint32_t)tg_tau[i] << 16);
+                    }
+                    dec_pay[it] = pw;
+                    atomicMax(&dec_key, key | (u64)(0xFF - it));  // equal keys: the lower item
                 }
-                if (rank < kD) {
-                    const u64 info = wl[(e >> 1) * kWa + kWInfo + (e & 1)];
-                    nx_key[rank] = me;
-                    nx_agent[rank] = kidx(me);
-                    nx_tau[rank] = (int)((info >> 16) & 0xFFFFu);
-                    nx_d[rank] = (int)(uint32_t)(info >> 32);
+            }
+        } else {
+            // the kD largest of the 2G published pending keys (unique), by rank; the ranks
+            // nobody holds keep the "none" written after the publication barrier
+            for (int e = t; e < 2 * G; e += 128) {
+                const u64 me = hi48(wl[(e >> 1) * kWa + kWPend + (e & 1)]);
+                if (me) {
+                    int rank = 0;
+#pragma unroll 4
+                    for (int qq = 0; qq < G; ++qq) {
+                        rank += hi48(wl[qq * kWa + kWPend]) > me;
+                        rank += hi48(wl[qq * kWa + kWPend + 1]) > me;
+                    }
+                    if (rank < kD) {
+                        const u64 info = wl[(e >> 1) * kWa + kWInfo + (e & 1)];
+                        nx[rank] = make_int4(kidx(me), (int)((info >> 16) & 0xFFFFu), (int)(uint32_t)(info >> 32), 0);
+                        if (rank == 0) nx_key0 = me;
+                    }
                 }
             }
         }
         __syncthreads();
 
         // ---- decide ---------------------------------------------------------------------------
+        int nx_agent[kD], nx_tau[kD], nx_d[kD];
+#pragma unroll
+        for (int dd = 0; dd < kD; ++dd) {
+            const int4 v = nx[dd];
+            nx_agent[dd] = v.x;
+            nx_tau[dd] = v.y;
+            nx_d[dd] = v.z;
+        }
+        const u64 pkey0 = nx_key0;
         u64 best = 0;
         int bj = -1, bk = -1, bj0 = -1;  // job, partner and own job of the best exchange
         {
-            const u64 mb = dec[0];
-            if (hi48(mb)) {
-                const int a = kidx(mb);
-                const u64 pw = wl[(a / kT) * kWa + kWPay];
-                best = hi48(mb);
+            const u64 win = dec_key;
+            if (hi48(win)) {
+                const u64 pw = dec_pay[0xFF - (int)(win & 0xFF)];
+                best = hi48(win);
                 bj = (int)((pw >> 48) & 0xFFFFu);
                 bk = (int)((pw >> 32) & 0xFFFFu);
                 bj0 = (int)((pw >> 16) & 0xFFFFu);
             }
         }
-#pragma unroll
-        for (int i = 0; i < kTargets; ++i) {
-            if (!(mask & (1u << i))) continue;
-            const u64 m = dec[1 + __popc(mask & ((1u << i) - 1))];
-            if (hi48(m) == 0) continue;
-            const u64 c = ak_key(kgain(m), tg_agent[i]);
-            if (c > best) {
-                best = c;
-                bj = kidx(m);
-                bk = (int)(m & 0xFF) * kT + (int)((m >> 8) & 0xFF);
-                bj0 = tg_tau[i];
-            }
-        }
         if (P.max_switches >= 0 && S >= P.max_switches) break;
-        const bool stall = nx_agent[0] >= 0 && nx_key[0] > best;  // pending bounds have gain > 0
+        const bool stall = nx_agent[0] >= 0 && pkey0 > best;  // pending bounds have gain > 0
         if (!stall && (best == 0 || kgain(best) <= 0)) break;
 
-        int is = -1, js = -1, k = -1, j0 = -1, gw = 0, dis = 0, dk = 0;
+        int is = -1, js = -1, k = -1, j0 = -1, gw = 0;
         if (!stall) {
             is = kidx(best);
             js = bj;
@@ -423,20 +447,19 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 if (t == 0) atomicOr(P.err, 2);  // cannot happen; never index with it
                 break;
             }
-            dis = P.A[(int64_t)is * nn + js];  // a[i*][j*]
-            dk = P.A[(int64_t)k * nn + j0];    // a[k][j0]
         }
 
         // ---- loads of the round: the switch's changed candidates and the re-evaluations ---
+        // Nothing loaded here is read before the owner rebuilds below, so every load of the
+        // round is in flight at once (the two new benefits are issued last: no wait for
+        // them may come before the other loads are issued).
         int a1 = 0, a2 = 0, w1 = 0, w2 = 0;
-        int tr2 = tr, dr2 = dr;  // job and benefit after this round's switch
+        int tr2 = tr;  // job after this round's switch
         if (mine && !stall) {
             if (r == is) {
                 tr2 = js;
-                dr2 = dis;
             } else if (r == k) {
                 tr2 = j0;
-                dr2 = dk;
             } else {
                 a1 = P.AT[(int64_t)js * nn + r];  // a[r][j*]
                 a2 = P.AT[(int64_t)j0 * nn + r];  // a[r][j0]
@@ -454,40 +477,57 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 rb[dd] = P.A[(int64_t)x * nn + tr2];          // a[x][tau(r)] after the switch
             }
         }
+        int dis = 0, dk = 0;
+        if (!stall) {
+            dis = P.A[(int64_t)is * nn + js];  // a[i*][j*]
+            dk = P.A[(int64_t)k * nn + j0];    // a[k][j0]
+        }
 
         // ---- owners rebuild the lists of this round's targets (while the loads are in flight)
+        // Done by the owner's wave alone: the bound is the largest workgroup second, the list
+        // the workgroup bests above it (the kM largest when there are more).
 #pragma unroll
         for (int i = 0; i < kTargets; ++i) {
             if (!(mask & (1u << i))) continue;
             const int x = tg_agent[i];
-            if (x / kT != q || x == is || x == k) continue;  // uniform across the workgroup
+            if (x < 0 || x / 64 != q * (kT / 64) + wave || x == is || x == k) continue;  // uniform across the wave
             const int sw = kWShare + 2 * __popc(mask & ((1u << i) - 1));
-            if (wave == 0) {
-                u64 m = 0;
-                for (int qq = lane; qq < G; qq += 64) m = umax64(m, hi48(wl[qq * kWa + sw + 1]));
-                m = wave_max(m);
-                if (lane == 0) {
-                    s_bnd = m;
-                    cand_n = 0;
+            u64 sec = 0;
+            for (int qq = lane; qq < G; qq += 64) sec = umax64(sec, hi48(wl[qq * kWa + sw + 1]));
+            const u64 bnd = wave_max(sec);
+            int cnt = 0;
+            for (int base = 0; base < G; base += 64) {
+                const int qq = base + lane;
+                const u64 w = qq < G ? wl[qq * kWa + sw] : 0;
+                const bool c = hi48(w) > bnd;
+                const u64 bal = __ballot(c);
+                if (c) rcand[wave][cnt + lanes_below(bal, lane)] = hi48(w) | (u64)(qq * kT + (int)((w >> 8) & 0xFF));
+                cnt += __popcll(bal);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            if (cnt > kM) {  // keep the kM largest; the next one joins the bound
+                for (int e = lane; e < cnt; e += 64) {
+                    const u64 me = rcand[wave][e];
+                    int rank = 0;
+                    for (int j = 0; j < cnt; ++j) rank += rcand[wave][j] > me;
+                    if (rank <= kM) rsel[wave][rank] = me;
                 }
-                if (lane <= kM) sel[lane] = 0;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             }
-            __syncthreads();
-            const u64 bnd = s_bnd;
-            for (int qq = t; qq < G; qq += kT) {
-                const u64 w = wl[qq * kWa + sw];
-                if (hi48(w) > bnd) cand[atomicAdd(&cand_n, 1)] = hi48(w) | (u64)(qq * kT + (int)((w >> 8) & 0xFF));
-            }
-            __syncthreads();
-            rank_select(cand, cand_n, sel);
-            __syncthreads();
             if (r == x) {
+                u64 extra = 0;
+                if (cnt > kM) {
 #pragma unroll
-                for (int e = 0; e < kM; ++e) L[e] = sel[e];
-                B = umax64(bnd, hi48(sel[kM]));
+                    for (int e = 0; e < kM; ++e) L[e] = rsel[wave][e];
+                    extra = rsel[wave][kM];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < kM; ++e) L[e] = e < cnt ? rcand[wave][e] : 0;
+                }
+                B = umax64(bnd, hi48(extra));
                 inflight = false;
             }
-            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // rcand is reused by the next slot
         }
 
         // ---- apply the switch to this workgroup's agents; shares for the next round -------
@@ -520,7 +560,8 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                     nsh[1] = le_key(g2, tr, t);
                 }
                 tr = tr2;
-                dr = dr2;
+                if (r == is) dr = dis;
+                if (r == k) dr = dk;
             }
         } else {
             ++stalls;
@@ -535,20 +576,15 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             if (mine && live && r == x) inflight = true;
         }
         refreshes += __popc(nmask >> 2);
-        __syncthreads();  // every thread has read this round's target slots and pending choices
-        if (t < kTargets) {
-            if (t == 0) {
-                tg_agent[0] = stall ? -1 : is;
-                tg_tau[0] = js;
-            } else if (t == 1) {
-                tg_agent[1] = stall ? -1 : k;
-                tg_tau[1] = j0;
-            } else {
-                const int dd = t - 2;
-                tg_agent[t] = (nmask >> t) & 1u ? nx_agent[dd] : -1;
-                tg_tau[t] = nx_tau[dd];
-                nx_agent[dd] = -1;
-            }
+        // next round's targets: the two switched agents, then the live pending agents
+        tg_agent[0] = stall ? -1 : is;
+        tg_tau[0] = js;
+        tg_agent[1] = stall ? -1 : k;
+        tg_tau[1] = j0;
+#pragma unroll
+        for (int dd = 0; dd < kD; ++dd) {
+            tg_agent[2 + dd] = (nmask >> (2 + dd)) & 1u ? nx_agent[dd] : -1;
+            tg_tau[2 + dd] = nx_tau[dd];
         }
         mask = nmask;
 #pragma unroll
