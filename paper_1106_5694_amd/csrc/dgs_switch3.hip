@@ -127,29 +127,25 @@ __device__ __forceinline__ u64 list_max(const u64 (&L)[kM]) {
 }
 
 // Insert exact candidate y; B (upper 48 bits only) bounds every candidate
-// outside the list.  y's job is not in the list.
+// outside the list.  y's job is not in the list.  Without branches: y takes
+// an empty slot, or evicts the smallest entry (which then joins the bound),
+// or stays outside and becomes the bound.
 __device__ __forceinline__ void list_insert(u64 (&L)[kM], u64 &B, u64 y) {
     const u64 yh = hi48(y);
-    if (yh <= B) return;
     u64 mn = L[0];
     int mi = 0;
 #pragma unroll
     for (int i = 1; i < kM; ++i) {
-        if (L[i] < mn) {
-            mn = L[i];
-            mi = i;
-        }
+        const bool lt = L[i] < mn;
+        mn = lt ? L[i] : mn;
+        mi = lt ? i : mi;
     }
-    if (mn != 0) {
-        if (yh < hi48(mn)) {  // below every entry of a full list: stays outside
-            B = yh;
-            return;
-        }
-        B = umax64(B, hi48(mn));  // evict the smallest entry
-    }
+    const u64 mh = hi48(mn);
+    const bool above = yh > B, full = mn != 0;
+    const bool take = above && (!full || yh >= mh);
+    B = (above && full) ? (yh < mh ? yh : umax64(B, mh)) : B;
 #pragma unroll
-    for (int i = 0; i < kM; ++i)
-        if (i == mi) L[i] = y;
+    for (int i = 0; i < kM; ++i) L[i] = (take && mi == i) ? y : L[i];
 }
 
 __device__ __forceinline__ void list_drop_jobs(u64 (&L)[kM], int j1, int j2) {
@@ -158,19 +154,6 @@ __device__ __forceinline__ void list_drop_jobs(u64 (&L)[kM], int j1, int j2) {
         const int j = kidx(L[i]);
         if (L[i] != 0 && (j == j1 || j == j2)) L[i] = 0;
     }
-}
-
-// Slot of the nth active target (nth < popcount(mask)); mask is uniform.
-__device__ __forceinline__ int nth_slot(uint32_t mask, int nth) {
-    int slot = 0;
-#pragma unroll
-    for (int i = 0; i < kTargets; ++i) {
-        if (mask & (1u << i)) {
-            if (nth == 0) slot = i;
-            --nth;
-        }
-    }
-    return slot;
 }
 
 // Number of lanes below this one whose bit is set in a wave ballot.
@@ -196,8 +179,12 @@ __device__ __forceinline__ void put_word(u64 *p, u64 w) {
     __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// NPER: gathered words per thread (G * kW <= NPER * kT).
+template <int NPER>
 __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
     extern __shared__ __align__(16) u64 wl[];  // gathered words, G x (words of the round)
+    // values reduced by this workgroup in a round: 0 best keys, 1 pending keys, 2 + j the
+    // shares for the round's j-th target (written at the end of the previous round)
     __shared__ u64 vals[2 + kTargets][kT];
     __shared__ u64 pay[kT];    // job, partner and own job of each agent's best exchange
     __shared__ u64 pinfo[kT];  // benefit and job of each agent
@@ -205,8 +192,10 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
     __shared__ u64 dec_pay[1 + kTargets];  // per item: job << 48 | partner << 32 | own job << 16
     __shared__ int4 nx[kD];                // pending agents chosen this round: agent (-1: none), job, benefit
     __shared__ u64 nx_key0;                // key of the first chosen pending agent (0: none)
+    __shared__ int2 tgc[2][kTargets];      // a round's targets (agent, job), by round parity
     __shared__ u64 rcand[kT / 64][kMaxG];  // per wave: candidates of a list being rebuilt
     __shared__ u64 rsel[kT / 64][kM + 1];
+    __shared__ u64 rlist[kTargets][kM + 1];  // rebuilt lists of the round's targets, then their bounds
     __shared__ int s_err;
 
     if (P.flags[0]) return;  // same decision in every workgroup
@@ -237,25 +226,16 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         B = b ? hi48(le_key(key_gain(b), key_index(b), 0)) : 0;
     }
     if (t == 0) s_err = 0;
-    // This round's target slots (uniform): agent (-1: inactive) and its job.
-    int tg_agent[kTargets], tg_tau[kTargets];
-#pragma unroll
-    for (int i = 0; i < kTargets; ++i) {
-        tg_agent[i] = -1;
-        tg_tau[i] = 0;
-    }
-    u64 sh[kTargets];  // this thread's shares for the target slots
-#pragma unroll
-    for (int i = 0; i < kTargets; ++i) sh[i] = 0;
-    uint32_t mask = 0;  // active target slots (uniform)
-    int64_t S = 0, gsum = 0, refreshes = 0, stalls = 0;
+    int nt = 0;  // targets of the round (uniform)
+    int S = 0, refreshes = 0, stalls = 0;
+    int64_t gsum = 0;
     __syncthreads();
 
     for (uint32_t s = 0;; ++s) {
         const uint32_t tag = s & 0xFFu;
-        const int nt = __popc(mask);
         const int kWa = kWShare + 2 * nt;  // words per workgroup this round
         u64 *buf = P.words + (size_t)(s & 1) * G * kW;
+        const int2 *tg = tgc[s & 1];
 
         // ---- this workgroup's words ------------------------------------------------------
         {
@@ -273,9 +253,6 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             }
             vals[0][t] = lk;
             vals[1][t] = pd;
-#pragma unroll
-            for (int i = 0; i < kTargets; ++i)
-                if (mask & (1u << i)) vals[2 + __popc(mask & ((1u << i) - 1))][t] = sh[i];
         }
         __syncthreads();
         // every thread has read the previous round's decision and pending choice
@@ -325,10 +302,10 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         {
             const int NW = G * kWa;
             const uint32_t magic = (uint32_t)((0x100000000ull + (uint64_t)kWa - 1) / (uint64_t)kWa);
-            u64 wv[kGatherPer];
-            int src[kGatherPer];
+            u64 wv[NPER];
+            int src[NPER];
 #pragma unroll
-            for (int i = 0; i < kGatherPer; ++i) {
+            for (int i = 0; i < NPER; ++i) {
                 const int x = t + i * kT;
                 const int qq = (int)__umulhi((uint32_t)x, magic);  // x / kWa (exact for x < 2^16)
                 src[i] = qq * kW + (x - qq * kWa);
@@ -338,7 +315,7 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             for (;;) {
                 bool ready = true;
 #pragma unroll
-                for (int i = 0; i < kGatherPer; ++i) ready &= (uint32_t)(wv[i] & 0xFFu) == tag;
+                for (int i = 0; i < NPER; ++i) ready &= (uint32_t)(wv[i] & 0xFFu) == tag;
                 if (ready) break;
                 if (++spins > kSpinLimit) {
                     s_err = 1;
@@ -347,14 +324,14 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 }
                 __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-                for (int i = 0; i < kGatherPer; ++i) {
+                for (int i = 0; i < NPER; ++i) {
                     const int x = t + i * kT;
                     if (x < NW && (uint32_t)(wv[i] & 0xFFu) != tag)
                         wv[i] = __hip_atomic_load(&buf[src[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
 #pragma unroll
-            for (int i = 0; i < kGatherPer; ++i) {
+            for (int i = 0; i < NPER; ++i) {
                 const int x = t + i * kT;
                 if (x < NW) wl[x] = wv[i];
             }
@@ -364,9 +341,9 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
 
         // ---- maxima over workgroups (waves 2-3), pending agents to re-evaluate (waves 0-1) ----
         if (wave >= 2) {
-            // item 0: best exchange; item 1 + j: best share of the j-th active target.  Each
-            // wave turns its items into decision candidates: a key (gain, agent) with the item
-            // number below it, and the exchange's job, partner and own job.
+            // item 0: best exchange; item 1 + j: best share of target j.  Each wave turns its
+            // items into decision candidates: a key (gain, agent) with the item number below
+            // it, and the exchange's job, partner and own job.
             for (int it = wave - 2; it <= nt; it += 2) {
                 const int widx = it == 0 ? kWBest : kWShare + 2 * (it - 1);
                 u64 m = 0;
@@ -378,11 +355,11 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                         key = hi48(m);
                         pw = wl[(kidx(m) / kT) * kWa + kWPay] & ~(u64)0xFFFF;
                     } else {
-                        const int i = nth_slot(mask, it - 1);
-                        key = ak_key(kgain(m), tg_agent[i]);
+                        const int2 x = tg[it - 1];
+                        key = ak_key(kgain(m), x.x);
                         const int partner = (int)(m & 0xFF) * kT + (int)((m >> 8) & 0xFF);
                         pw = ((u64)(uint32_t)kidx(m) << 48) | ((u64)(uint32_t)partner << 32) |
-                             ((u64)(uint32_t)tg_tau[i] << 16);
+                             ((u64)(uint32_t)x.y << 16);
                     }
                     dec_pay[it] = pw;
                     atomicMax(&dec_key, key | (u64)(0xFF - it));  // equal keys: the lower item
@@ -415,7 +392,7 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
 #pragma unroll
         for (int dd = 0; dd < kD; ++dd) {
             const int4 v = nx[dd];
-            nx_agent[dd] = v.x;
+            nx_agent[dd] = __builtin_amdgcn_readfirstlane(v.x);  // uniform
             nx_tau[dd] = v.y;
             nx_d[dd] = v.z;
         }
@@ -485,13 +462,14 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
 
         // ---- owners rebuild the lists of this round's targets (while the loads are in flight)
         // Done by the owner's wave alone: the bound is the largest workgroup second, the list
-        // the workgroup bests above it (the kM largest when there are more).
-#pragma unroll
-        for (int i = 0; i < kTargets; ++i) {
-            if (!(mask & (1u << i))) continue;
-            const int x = tg_agent[i];
-            if (x < 0 || x / 64 != q * (kT / 64) + wave || x == is || x == k) continue;  // uniform across the wave
-            const int sw = kWShare + 2 * __popc(mask & ((1u << i) - 1));
+        // the workgroup bests above it (the kM largest when there are more).  The new list
+        // goes through LDS to its owner.
+        int myj = -1;  // this thread's rebuilt target, if any
+#pragma unroll 1
+        for (int j = 0; j < nt; ++j) {
+            const int x = tg[j].x;
+            if (x / 64 != q * (kT / 64) + wave || x == is || x == k) continue;  // uniform across the wave
+            const int sw = kWShare + 2 * j;
             u64 sec = 0;
             for (int qq = lane; qq < G; qq += 64) sec = umax64(sec, hi48(wl[qq * kWa + sw + 1]));
             const u64 bnd = wave_max(sec);
@@ -509,86 +487,78 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 for (int e = lane; e < cnt; e += 64) {
                     const u64 me = rcand[wave][e];
                     int rank = 0;
-                    for (int j = 0; j < cnt; ++j) rank += rcand[wave][j] > me;
+                    for (int i = 0; i < cnt; ++i) rank += rcand[wave][i] > me;
                     if (rank <= kM) rsel[wave][rank] = me;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             }
-            if (r == x) {
-                u64 extra = 0;
-                if (cnt > kM) {
-#pragma unroll
-                    for (int e = 0; e < kM; ++e) L[e] = rsel[wave][e];
-                    extra = rsel[wave][kM];
-                } else {
-#pragma unroll
-                    for (int e = 0; e < kM; ++e) L[e] = e < cnt ? rcand[wave][e] : 0;
-                }
-                B = umax64(bnd, hi48(extra));
-                inflight = false;
+            if (lane <= kM) {
+                u64 v;
+                if (cnt > kM)
+                    v = lane < kM ? rsel[wave][lane] : umax64(bnd, hi48(rsel[wave][kM]));
+                else
+                    v = lane < kM ? (lane < cnt ? rcand[wave][lane] : 0) : bnd;
+                rlist[j][lane] = v;
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // rcand is reused by the next slot
+            if (r == x) myj = j;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // rlist is written; rcand is reused
+        }
+        if (myj >= 0) {
+#pragma unroll
+            for (int e = 0; e < kM; ++e) L[e] = rlist[myj][e];
+            B = rlist[myj][kM];
+            inflight = false;
         }
 
-        // ---- apply the switch to this workgroup's agents; shares for the next round -------
-        u64 nsh[kTargets];
-#pragma unroll
-        for (int i = 0; i < kTargets; ++i) nsh[i] = 0;
+        // ---- apply the switch; shares for the next round's targets ---------------------------
+        // Targets of the next round: i* (share g(r, i*)), k (g(r, k)), then the live pending
+        // agents chosen in this round.  Shares go straight to vals.
+        int2 *tgn = tgc[(s + 1) & 1];
+        int jn = 0;
         if (!stall) {
             ++S;
             gsum += gw;
+            u64 s0 = 0, s1 = 0;
             if (mine) {
-                if (r == is) {
-                    nsh[1] = le_key(-gw, js, t);  // g(i*, k) after the switch
+                const int g1 = (a1 + w1) - (dr + dis);  // g(r, i*)
+                const int g2 = (a2 + w2) - (dr + dk);   // g(r, k)
+                const bool switched = r == is || r == k;
+                list_drop_jobs(L, js, j0);
+                list_insert(L, B, le_key(g1, js, is));
+                list_insert(L, B, le_key(g2, j0, k));
 #pragma unroll
-                    for (int i = 0; i < kM; ++i) L[i] = 0;
-                    B = 0;
-                    inflight = false;
-                } else if (r == k) {
-                    nsh[0] = le_key(-gw, j0, t);  // g(k, i*) after the switch
-#pragma unroll
-                    for (int i = 0; i < kM; ++i) L[i] = 0;
-                    B = 0;
-                    inflight = false;
-                } else {
-                    const int g1 = (a1 + w1) - (dr + dis);  // g(r, i*)
-                    const int g2 = (a2 + w2) - (dr + dk);   // g(r, k)
-                    list_drop_jobs(L, js, j0);
-                    list_insert(L, B, le_key(g1, js, is));
-                    list_insert(L, B, le_key(g2, j0, k));
-                    nsh[0] = le_key(g1, tr, t);
-                    nsh[1] = le_key(g2, tr, t);
-                }
+                for (int i = 0; i < kM; ++i) L[i] = switched ? 0 : L[i];
+                B = switched ? 0 : B;
+                inflight = switched ? false : inflight;
+                s0 = r == is ? 0 : (r == k ? le_key(-gw, j0, t) : le_key(g1, tr, t));  // g(k, i*) after the switch
+                s1 = r == k ? 0 : (r == is ? le_key(-gw, js, t) : le_key(g2, tr, t));  // g(i*, k) after the switch
                 tr = tr2;
-                if (r == is) dr = dis;
-                if (r == k) dr = dk;
+                dr = r == is ? dis : (r == k ? dk : dr);
             }
+            vals[2][t] = s0;
+            vals[3][t] = s1;
+            if (t == 0) {
+                tgn[0] = make_int2(is, js);
+                tgn[1] = make_int2(k, j0);
+            }
+            jn = 2;
         } else {
             ++stalls;
         }
-        uint32_t nmask = stall ? 0u : 3u;
 #pragma unroll
         for (int dd = 0; dd < kD; ++dd) {
             const int x = nx_agent[dd];
-            const bool live = x >= 0 && x != is && x != k;
-            if (live) nmask |= 1u << (2 + dd);
-            if (mine && live && r != x) nsh[2 + dd] = le_key((ra[dd] + rb[dd]) - (dr + nx_d[dd]), tr, t);  // g(r, x)
-            if (mine && live && r == x) inflight = true;
+            if (x >= 0 && x != is && x != k) {  // uniform
+                u64 v = 0;
+                if (mine && r != x) v = le_key((ra[dd] + rb[dd]) - (dr + nx_d[dd]), tr, t);  // g(r, x)
+                if (mine && r == x) inflight = true;
+                vals[2 + jn][t] = v;
+                if (t == 0) tgn[jn] = make_int2(x, nx_tau[dd]);
+                ++jn;
+            }
         }
-        refreshes += __popc(nmask >> 2);
-        // next round's targets: the two switched agents, then the live pending agents
-        tg_agent[0] = stall ? -1 : is;
-        tg_tau[0] = js;
-        tg_agent[1] = stall ? -1 : k;
-        tg_tau[1] = j0;
-#pragma unroll
-        for (int dd = 0; dd < kD; ++dd) {
-            tg_agent[2 + dd] = (nmask >> (2 + dd)) & 1u ? nx_agent[dd] : -1;
-            tg_tau[2 + dd] = nx_tau[dd];
-        }
-        mask = nmask;
-#pragma unroll
-        for (int i = 0; i < kTargets; ++i) sh[i] = nsh[i];
+        refreshes += jn - (stall ? 0 : 2);
+        nt = jn;
     }
 
     if (mine) P.tau[r] = tr;
@@ -624,14 +594,13 @@ hipError_t launch_switch_v3(const Instance &I, int64_t max_switches, void *words
     const int grid = switch_v3_grid(I.n);
     if (grid < 1 || grid > kMaxG) return hipErrorInvalidValue;
     const size_t shm = (size_t)grid * kW * sizeof(u64);
-    hipError_t e = hipFuncSetAttribute((const void *)k_switch_v3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    // the narrow gather when every workgroup's words fit 8 per thread
+    const void *kern = grid * kW <= 8 * kT ? (const void *)k_switch_v3<8> : (const void *)k_switch_v3<kGatherPer>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
-    if (!coop) {
-        hipLaunchKernelGGL(k_switch_v3, dim3((unsigned)grid), dim3(kT), shm, s, P);
-        return hipGetLastError();
-    }
     void *args[] = {&P};
-    return hipLaunchCooperativeKernel((const void *)k_switch_v3, dim3((unsigned)grid), dim3(kT), args, (unsigned)shm, s);
+    if (!coop) return hipLaunchKernel(kern, dim3((unsigned)grid), dim3(kT), args, shm, s);
+    return hipLaunchCooperativeKernel(kern, dim3((unsigned)grid), dim3(kT), args, (unsigned)shm, s);
 }
 
 }  // namespace dgs
