@@ -393,9 +393,12 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         for (int dd = 0; dd < kD; ++dd) {
             const int4 v = nx[dd];
             nx_agent[dd] = __builtin_amdgcn_readfirstlane(v.x);  // uniform
-            nx_tau[dd] = v.y;
+            nx_tau[dd] = __builtin_amdgcn_readfirstlane(v.y);
             nx_d[dd] = v.z;
         }
+        int nref = 0;  // the chosen pending agents are a prefix
+#pragma unroll
+        for (int dd = 0; dd < kD; ++dd) nref += nx_agent[dd] >= 0;
         const u64 pkey0 = nx_key0;
         u64 best = 0;
         int bj = -1, bk = -1, bj0 = -1;  // job, partner and own job of the best exchange
@@ -430,26 +433,24 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         // Nothing loaded here is read before the owner rebuilds below, so every load of the
         // round is in flight at once (the two new benefits are issued last: no wait for
         // them may come before the other loads are issued).
-        int a1 = 0, a2 = 0, w1 = 0, w2 = 0;
         int tr2 = tr;  // job after this round's switch
-        if (mine && !stall) {
-            if (r == is) {
-                tr2 = js;
-            } else if (r == k) {
-                tr2 = j0;
-            } else {
-                a1 = P.AT[(int64_t)js * nn + r];  // a[r][j*]
-                a2 = P.AT[(int64_t)j0 * nn + r];  // a[r][j0]
-                w1 = P.A[(int64_t)is * nn + tr];  // a[i*][tau(r)]
-                w2 = P.A[(int64_t)k * nn + tr];   // a[k][tau(r)]
-            }
+        if (mine && !stall) tr2 = r == is ? js : (r == k ? j0 : tr);
+        int a1 = 0, a2 = 0, w1 = 0, w2 = 0;
+        if (mine && !stall && r != is && r != k) {
+            a1 = P.AT[(int64_t)js * nn + r];  // a[r][j*]
+            a2 = P.AT[(int64_t)j0 * nn + r];  // a[r][j0]
+            w1 = P.A[(int64_t)is * nn + tr];  // a[i*][tau(r)]
+            w2 = P.A[(int64_t)k * nn + tr];   // a[k][tau(r)]
         }
+        // (No branch may merge paths that hold loaded values in different registers: the
+        // copy at the merge would wait for the loads.)
         int ra[kD], rb[kD];
 #pragma unroll
         for (int dd = 0; dd < kD; ++dd) {
             const int x = nx_agent[dd];
+            const bool ok = dd < nref && mine && x != is && x != k && r != x;
             ra[dd] = rb[dd] = 0;
-            if (mine && x >= 0 && x != is && x != k && r != x) {
+            if (ok) {
                 ra[dd] = P.AT[(int64_t)nx_tau[dd] * nn + r];  // a[r][tau(x)]
                 rb[dd] = P.A[(int64_t)x * nn + tr2];          // a[x][tau(r)] after the switch
             }
@@ -548,7 +549,7 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
 #pragma unroll
         for (int dd = 0; dd < kD; ++dd) {
             const int x = nx_agent[dd];
-            if (x >= 0 && x != is && x != k) {  // uniform
+            if (dd < nref && x != is && x != k) {  // uniform
                 u64 v = 0;
                 if (mine && r != x) v = le_key((ra[dd] + rb[dd]) - (dr + nx_d[dd]), tr, t);  // g(r, x)
                 if (mine && r == x) inflight = true;
