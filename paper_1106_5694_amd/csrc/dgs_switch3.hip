@@ -93,20 +93,53 @@ __device__ __forceinline__ uint32_t dppu(uint32_t v) {
 }
 __device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
-__device__ __forceinline__ uint32_t wave_max32(uint32_t v) {
+// The four DPP steps: afterwards every 16-lane row holds its maximum.
+__device__ __forceinline__ uint32_t row_fold(uint32_t v) {
     v = umax32(v, dppu<kDppXor1>(v));
     v = umax32(v, dppu<kDppXor2>(v));
     v = umax32(v, dppu<kDppHalfMirror>(v));
     v = umax32(v, dppu<kDppMirror>(v));
+    return v;
+}
+__device__ __forceinline__ uint32_t rows_max(uint32_t v) {
     const uint32_t a = umax32((uint32_t)__builtin_amdgcn_readlane((int)v, 0), (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
     const uint32_t b = umax32((uint32_t)__builtin_amdgcn_readlane((int)v, 32), (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
     return umax32(a, b);
 }
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v) { return rows_max(row_fold(v)); }
 
 __device__ __forceinline__ u64 wave_max(u64 v) {
     const uint32_t hi = wave_max32((uint32_t)(v >> 32));
     const uint32_t lo = wave_max32((uint32_t)(v >> 32) == hi ? (uint32_t)v : 0u);
     return ((u64)hi << 32) | lo;
+}
+
+// Two independent 64-bit maxima, their steps interleaved (the DPP steps of one
+// fill the other's wait states).
+__device__ __forceinline__ void wave_max_pair(u64 &a, u64 &b) {
+    const uint32_t ah = (uint32_t)(a >> 32), bh = (uint32_t)(b >> 32);
+    uint32_t x = ah, y = bh;
+    x = umax32(x, dppu<kDppXor1>(x));
+    y = umax32(y, dppu<kDppXor1>(y));
+    x = umax32(x, dppu<kDppXor2>(x));
+    y = umax32(y, dppu<kDppXor2>(y));
+    x = umax32(x, dppu<kDppHalfMirror>(x));
+    y = umax32(y, dppu<kDppHalfMirror>(y));
+    x = umax32(x, dppu<kDppMirror>(x));
+    y = umax32(y, dppu<kDppMirror>(y));
+    const uint32_t HA = rows_max(x), HB = rows_max(y);
+    x = ah == HA ? (uint32_t)a : 0u;
+    y = bh == HB ? (uint32_t)b : 0u;
+    x = umax32(x, dppu<kDppXor1>(x));
+    y = umax32(y, dppu<kDppXor1>(y));
+    x = umax32(x, dppu<kDppXor2>(x));
+    y = umax32(y, dppu<kDppXor2>(y));
+    x = umax32(x, dppu<kDppHalfMirror>(x));
+    y = umax32(y, dppu<kDppHalfMirror>(y));
+    x = umax32(x, dppu<kDppMirror>(x));
+    y = umax32(y, dppu<kDppMirror>(y));
+    a = ((u64)HA << 32) | rows_max(x);
+    b = ((u64)HB << 32) | rows_max(y);
 }
 
 // Top-2 over the wave; every lane holds a1 >= a2, keys unique apart from zeros.
@@ -115,6 +148,18 @@ __device__ __forceinline__ void wave_top2(u64 &a1, u64 &a2) {
     const u64 m2 = wave_max(a1 == m1 ? a2 : a1);
     a1 = m1;
     a2 = m2;
+}
+
+// Two independent top-2 reductions, interleaved.
+__device__ __forceinline__ void wave_top2_pair(u64 &a1, u64 &a2, u64 &b1, u64 &b2) {
+    u64 ma = a1, mb = b1;
+    wave_max_pair(ma, mb);
+    u64 sa = a1 == ma ? a2 : a1, sb = b1 == mb ? b2 : b1;
+    wave_max_pair(sa, sb);
+    a1 = ma;
+    a2 = sa;
+    b1 = mb;
+    b2 = sb;
 }
 
 // ---- candidate lists (registers) --------------------------------------------------------
@@ -193,6 +238,8 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
     __shared__ int4 nx[kD];                // pending agents chosen this round: agent (-1: none), job, benefit
     __shared__ u64 nx_key0;                // key of the first chosen pending agent (0: none)
     __shared__ int2 tgc[2][kTargets];      // a round's targets (agent, job), by round parity
+    __shared__ u64 pend[kD];               // wave 0: the pending keys when there are at most kD
+    __shared__ int pend_at[kD];
     __shared__ u64 rcand[kT / 64][kMaxG];  // per wave: candidates of a list being rebuilt
     __shared__ u64 rsel[kT / 64][kM + 1];
     __shared__ u64 rlist[kTargets][kM + 1];  // rebuilt lists of the round's targets, then their bounds
@@ -261,30 +308,29 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             nx_key0 = 0;
         }
         if (t < kD) nx[t] = make_int4(-1, 0, 0, 0);
-        // wave w reduces value types w, w + 4, ...: 0 best (max), 1 pending (top-2), 2 + j shares
-        // (top-2).  Word w of a workgroup always sits at the same place and is always written by
-        // the same lane, every round (share words of inactive targets carry only the tag), so no
-        // older word with a matching tag can be left anywhere in the buffer.
-        for (int ty = wave; ty < 2 + kTargets; ty += 4) {
-            if (ty >= 2 + nt) {
-                if (lane < 2) put_word(&buf[(size_t)q * kW + kWShare + 2 * (ty - 2) + lane], (u64)tag);
-            } else if (ty == 0) {
-                u64 a = umax64(umax64(vals[0][lane], vals[0][lane + 64]),
-                               umax64(vals[0][lane + 128], vals[0][lane + 192]));
-                a = wave_max(a);
-                if (lane == 0) {
-                    const u64 w1 = a ? pay[kidx(a) - q * kT] : 0;
-                    put_word(&buf[(size_t)q * kW + kWBest], a | tag);
-                    put_word(&buf[(size_t)q * kW + kWPay], (w1 & ~(u64)0xFF) | tag);
-                }
-            } else {
-                u64 a1 = vals[ty][lane], a2 = 0;
-                top2_push(a1, a2, vals[ty][lane + 64]);
-                top2_push(a1, a2, vals[ty][lane + 128]);
-                top2_push(a1, a2, vals[ty][lane + 192]);
-                wave_top2(a1, a2);
-                if (lane < 2) {
-                    const u64 v = lane == 0 ? a1 : a2;
+        // wave w reduces value types w, w + 4 (together) and w + 8: 0 best, 1 pending (top-2),
+        // 2 + j shares (top-2).  Word w of a workgroup always sits at the same place and is
+        // always written by the same lane, every round (share words of inactive targets carry
+        // only the tag), so no older word with a matching tag can be left anywhere in the buffer.
+        {
+            auto gather4 = [&](int ty, u64 &v1, u64 &v2) {
+                v1 = vals[ty][lane];
+                v2 = 0;
+                top2_push(v1, v2, vals[ty][lane + 64]);
+                top2_push(v1, v2, vals[ty][lane + 128]);
+                top2_push(v1, v2, vals[ty][lane + 192]);
+            };
+            auto publish = [&](int ty, u64 v1, u64 v2) {
+                if (ty >= 2 + nt) {
+                    if (lane < 2) put_word(&buf[(size_t)q * kW + kWShare + 2 * (ty - 2) + lane], (u64)tag);
+                } else if (ty == 0) {
+                    if (lane == 0) {
+                        const u64 w1 = v1 ? pay[kidx(v1) - q * kT] : 0;
+                        put_word(&buf[(size_t)q * kW + kWBest], v1 | tag);
+                        put_word(&buf[(size_t)q * kW + kWPay], (w1 & ~(u64)0xFF) | tag);
+                    }
+                } else if (lane < 2) {
+                    const u64 v = lane == 0 ? v1 : v2;
                     if (ty == 1) {
                         const u64 info = v ? pinfo[kidx(v) - q * kT] : 0;
                         put_word(&buf[(size_t)q * kW + kWPend + lane], v | tag);
@@ -294,7 +340,20 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                         put_word(&buf[(size_t)q * kW + kWShare + 2 * (ty - 2) + lane], w | tag);
                     }
                 }
+            };
+            const int tA = wave, tB = wave + 4, tC = wave + 8;  // tA < 2 always holds for waves 0, 1
+            u64 a1 = 0, a2 = 0, b1 = 0, b2 = 0;
+            if (tA < 2 + nt) gather4(tA, a1, a2);
+            if (tB < 2 + nt) gather4(tB, b1, b2);
+            wave_top2_pair(a1, a2, b1, b2);
+            publish(tA, a1, a2);
+            publish(tB, b1, b2);
+            u64 c1 = 0, c2 = 0;
+            if (tC < 2 + nt) {
+                gather4(tC, c1, c2);
+                wave_top2(c1, c2);
             }
+            publish(tC, c1, c2);
         }
 
         // ---- gather every workgroup's words ------------------------------------------------
@@ -339,48 +398,90 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         __syncthreads();
         if (s_err) break;
 
-        // ---- maxima over workgroups (waves 2-3), pending agents to re-evaluate (waves 0-1) ----
-        if (wave >= 2) {
+        // ---- maxima over workgroups (waves 1-3), pending agents to re-evaluate (wave 0) -----
+        if (wave > 0) {
             // item 0: best exchange; item 1 + j: best share of target j.  Each wave turns its
             // items into decision candidates: a key (gain, agent) with the item number below
-            // it, and the exchange's job, partner and own job.
-            for (int it = wave - 2; it <= nt; it += 2) {
+            // it, and the exchange's job, partner and own job.  Items go in pairs.
+            auto item_max = [&](int it) {
                 const int widx = it == 0 ? kWBest : kWShare + 2 * (it - 1);
                 u64 m = 0;
                 for (int qq = lane; qq < G; qq += 64) m = umax64(m, (wl[qq * kWa + widx] & ~(u64)0xFF) | (u64)qq);
-                m = wave_max(m);
-                if (hi48(m) != 0 && lane == 0) {
-                    u64 key, pw;
-                    if (it == 0) {
-                        key = hi48(m);
-                        pw = wl[(kidx(m) / kT) * kWa + kWPay] & ~(u64)0xFFFF;
-                    } else {
-                        const int2 x = tg[it - 1];
-                        key = ak_key(kgain(m), x.x);
-                        const int partner = (int)(m & 0xFF) * kT + (int)((m >> 8) & 0xFF);
-                        pw = ((u64)(uint32_t)kidx(m) << 48) | ((u64)(uint32_t)partner << 32) |
-                             ((u64)(uint32_t)x.y << 16);
-                    }
-                    dec_pay[it] = pw;
-                    atomicMax(&dec_key, key | (u64)(0xFF - it));  // equal keys: the lower item
+                return m;
+            };
+            auto commit = [&](int it, u64 m) {
+                if (hi48(m) == 0) return;
+                u64 key, pw;
+                if (it == 0) {
+                    key = hi48(m);
+                    pw = wl[(kidx(m) / kT) * kWa + kWPay] & ~(u64)0xFFFF;
+                } else {
+                    const int2 x = tg[it - 1];
+                    key = ak_key(kgain(m), x.x);
+                    const int partner = (int)(m & 0xFF) * kT + (int)((m >> 8) & 0xFF);
+                    pw = ((u64)(uint32_t)kidx(m) << 48) | ((u64)(uint32_t)partner << 32) | ((u64)(uint32_t)x.y << 16);
+                }
+                dec_pay[it] = pw;
+                atomicMax(&dec_key, key | (u64)(0xFF - it));  // equal keys: the lower item
+            };
+            for (int i0 = wave - 1; i0 <= nt; i0 += 6) {
+                const int i1 = i0 + 3;
+                u64 m0 = item_max(i0), m1 = i1 <= nt ? item_max(i1) : 0;
+                wave_max_pair(m0, m1);
+                if (lane == 0) {
+                    commit(i0, m0);
+                    if (i1 <= nt) commit(i1, m1);
                 }
             }
         } else {
-            // the kD largest of the 2G published pending keys (unique), by rank; the ranks
-            // nobody holds keep the "none" written after the publication barrier
-            for (int e = t; e < 2 * G; e += 128) {
-                const u64 me = hi48(wl[(e >> 1) * kWa + kWPend + (e & 1)]);
-                if (me) {
-                    int rank = 0;
-#pragma unroll 4
-                    for (int qq = 0; qq < G; ++qq) {
-                        rank += hi48(wl[qq * kWa + kWPend]) > me;
-                        rank += hi48(wl[qq * kWa + kWPend + 1]) > me;
+            // the kD largest of the 2G published pending keys (unique); the ranks nobody holds
+            // keep the "none" written after the publication barrier
+            constexpr int kPer = (2 * (NPER * kT / kW) + 63) / 64;  // keys per lane: G <= NPER * kT / kW
+            u64 kk[kPer];
+            int m = 0;
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int e = lane + 64 * i;
+                kk[i] = e < 2 * G ? hi48(wl[(e >> 1) * kWa + kWPend + (e & 1)]) : 0;
+                m += __popcll(__ballot(kk[i] != 0));
+            }
+            auto choose = [&](int rank, u64 key, int e) {
+                const u64 info = wl[(e >> 1) * kWa + kWInfo + (e & 1)];
+                nx[rank] = make_int4(kidx(key), (int)((info >> 16) & 0xFFFFu), (int)(uint32_t)(info >> 32), 0);
+                if (rank == 0) nx_key0 = key;
+            };
+            if (m <= kD) {  // all of them: compact, then rank among themselves
+                int c = 0;
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const u64 bal = __ballot(kk[i] != 0);
+                    if (kk[i]) {
+                        const int at = c + lanes_below(bal, lane);
+                        pend[at] = kk[i];
+                        pend_at[at] = lane + 64 * i;
                     }
-                    if (rank < kD) {
-                        const u64 info = wl[(e >> 1) * kWa + kWInfo + (e & 1)];
-                        nx[rank] = make_int4(kidx(me), (int)((info >> 16) & 0xFFFFu), (int)(uint32_t)(info >> 32), 0);
-                        if (rank == 0) nx_key0 = me;
+                    c += __popcll(bal);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                if (lane < m) {
+                    const u64 me = pend[lane];
+                    int rank = 0;
+#pragma unroll
+                    for (int i = 0; i < kD; ++i) rank += i < m && pend[i] > me;
+                    choose(rank, me, pend_at[lane]);
+                }
+            } else {  // the kD largest by repeated maxima
+                for (int rank = 0; rank < kD; ++rank) {
+                    u64 mx = 0;
+#pragma unroll
+                    for (int i = 0; i < kPer; ++i) mx = umax64(mx, kk[i]);
+                    const u64 top = wave_max(mx);
+#pragma unroll
+                    for (int i = 0; i < kPer; ++i) {
+                        if (kk[i] == top) {  // one lane, one slot: keys are unique
+                            choose(rank, top, lane + 64 * i);
+                            kk[i] = 0;
+                        }
                     }
                 }
             }
