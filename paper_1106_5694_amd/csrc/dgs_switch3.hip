@@ -567,10 +567,17 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         // the workgroup bests above it (the kM largest when there are more).  The new list
         // goes through LDS to its owner.
         int myj = -1;  // this thread's rebuilt target, if any
+        uint32_t own = 0;  // targets whose owner is in this wave (uniform)
+#pragma unroll
+        for (int j = 0; j < kTargets; ++j) {
+            const int x = tg[j].x;
+            if (j < nt && x / 64 == q * (kT / 64) + wave && x != is && x != k) own |= 1u << j;
+        }
+        own = __builtin_amdgcn_readfirstlane(own);
 #pragma unroll 1
         for (int j = 0; j < nt; ++j) {
+            if (!((own >> j) & 1u)) continue;
             const int x = tg[j].x;
-            if (x / 64 != q * (kT / 64) + wave || x == is || x == k) continue;  // uniform across the wave
             const int sw = kWShare + 2 * j;
             u64 sec = 0;
             for (int qq = lane; qq < G; qq += 64) sec = umax64(sec, hi48(wl[qq * kWa + sw + 1]));
