@@ -7,6 +7,11 @@ compare against these numbers because the oracle needs minutes at this
 size.  Run from the repository root:
 
     python tests/golden/make_golden.py [seeds...]
+
+With ``--prefix`` it writes tests/golden/lowrank20480_prefix.txt instead:
+the oracle's state after the first 1000 switches of the n = 20480 instance
+(seed 1), a size whose switching launch gathers more than 8 exchange words
+per thread.
 """
 from __future__ import annotations
 
@@ -24,6 +29,8 @@ import oracle  # noqa: E402
 from workloads import gen  # noqa: E402
 
 OUT = os.path.join(HERE, "lowrank16384.txt")
+OUT_PREFIX = os.path.join(HERE, "lowrank20480_prefix.txt")
+PREFIX_N, PREFIX_K = 20480, 1000
 
 
 def main(seeds):
@@ -46,5 +53,24 @@ def main(seeds):
         f.write("\n".join(lines) + "\n")
 
 
+def prefix(seed=1):
+    t0 = time.time()
+    A = gen.lowrank_matrix(PREFIX_N, seed)
+    g = oracle.greedy(A)
+    r = oracle.dgs_incr(A, init=g, max_switches=PREFIX_K)
+    h = hashlib.sha256(np.ascontiguousarray(r["tau"], dtype="<i4").tobytes()).hexdigest()
+    lines = [f"# Oracle state after the first {PREFIX_K} switches (greedy start) of the",
+             f"# n = {PREFIX_N} low-rank-plus-noise workload (workloads.gen.lowrank_matrix({PREFIX_N}, seed)),",
+             "# written by make_golden.py --prefix with the C oracle's incremental DGS.",
+             "", f"[seed{seed}]", f"n = {PREFIX_N}", f"k = {PREFIX_K}", f"greedy_f = {oracle.objective(A, g)}",
+             f"f = {r['f']}", f"S = {r['S']}", f"tau_sha256 = {h}"]
+    with open(OUT_PREFIX, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"prefix seed {seed}: S={r['S']} f={r['f']} ({time.time() - t0:.0f} s)", flush=True)
+
+
 if __name__ == "__main__":
-    main([int(s) for s in sys.argv[1:]] or [1, 2, 3, 4, 5])
+    if sys.argv[1:2] == ["--prefix"]:
+        prefix()
+    else:
+        main([int(s) for s in sys.argv[1:]] or [1, 2, 3, 4, 5])

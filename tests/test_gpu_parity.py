@@ -183,6 +183,33 @@ def test_lowrank16384(dgs, seed):
         assert g.max() <= 0
 
 
+def test_lowrank20480_wide_gather(dgs):
+    """n = 20480 takes 80 switching workgroups, the kernel variant that
+    gathers more than 8 exchange words per thread.  Its first 1000 switches
+    match the oracle's (stored by make_golden.py --prefix); a full run ends
+    with a permutation that has no improving exchange on sampled agents."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "lowrank20480_prefix.txt")
+    if not os.path.exists(path):
+        pytest.skip("golden values not generated")
+    gold = read_sections("lowrank20480_prefix.txt")["seed1"]
+    n, k = int(gold["n"]), int(gold["k"])
+    say(f"case lowrank{n} seed 1 prefix k={k} and full run")
+    A = gen.lowrank_matrix(n, 1)
+    tau, res = dgs.solve(A, max_switches=k)
+    assert res["initial_benefit"] == int(gold["greedy_f"])
+    assert res["total_benefit"] == int(gold["f"]) and res["switches"] == int(gold["S"])
+    h = hashlib.sha256(np.ascontiguousarray(tau, dtype="<i4").tobytes()).hexdigest()
+    assert h == gold["tau_sha256"]
+    tau2, res2 = dgs.solve(A)
+    assert oracle.is_permutation(tau2)
+    assert res2["total_benefit"] > res["total_benefit"] and res2["switches"] > k
+    d = A[np.arange(n), tau2].astype(np.int64)
+    assert int(d.sum()) == res2["total_benefit"]
+    for i in gen.permutation(n, 7)[:64]:
+        g = (A[i, tau2].astype(np.int64) + A[:, tau2[i]].astype(np.int64)) - (d[i] + d)
+        assert g.max() <= 0
+
+
 def test_batched_equals_solo(dgs):
     ns = [64, 1, 2, 300, 1000, 65, 777]
     As = [gen.uniform_matrix(n, 0, 10000, 40 + i) for i, n in enumerate(ns)]
