@@ -59,6 +59,89 @@ __device__ __forceinline__ u64 wave_merge_top(u64 a, u64 b, int lane) {
     return wave_bitonic_desc(kmax(a, reverse_lanes64(b)), lane);
 }
 
+// The kRound best keys (benefit, job) of the free columns [c0, c1) of row Ar,
+// c1 - c0 <= 64 * kSel, sorted descending across the wave.  Every lane holds
+// its columns' keys in registers; a binary search on the benefit (the high
+// word of the key) finds the largest threshold T with at least kRound keys at
+// or above it: those keys contain the best kRound.  When they number at most
+// 2 kRound they are compacted into `buf` (this wave's 2 x 64 LDS slots) and
+// sorted; otherwise (many equal benefits at T) the keys are merged in batches.
+constexpr int kSel = 16;  // keys per lane
+
+__device__ __forceinline__ int count_at_least(const uint32_t (&h)[kSel], uint32_t T) {
+    int c = 0;
+#pragma unroll
+    for (int u = 0; u < kSel; ++u) c += __popcll(__ballot(h[u] >= T));
+    return c;
+}
+
+__device__ u64 wave_top_select(const int32_t *Ar, const uint32_t *taken, int c0, int c1, int lane, u64 *buf) {
+    u64 key[kSel];
+    uint32_t h[kSel];  // benefit part of each key (0: none)
+#pragma unroll
+    for (int u = 0; u < kSel; ++u) {
+        const int c = c0 + u * 64 + lane;
+        bool ok = false;
+        int v = 0;
+        if (c < c1) {
+            ok = !((taken[c >> 5] >> (c & 31)) & 1u);
+            v = Ar[c];
+        }
+        key[u] = ok ? mk_key(v, c) : 0;
+        h[u] = (uint32_t)(key[u] >> 32);
+    }
+    // threshold: the largest T with count(h >= T) >= kRound (T = 1 takes every key)
+    uint32_t T = 1;
+    if (count_at_least(h, 1) > kRound) {
+        uint32_t lo = 0xFFFFFFFFu, hi = 0;
+#pragma unroll
+        for (int u = 0; u < kSel; ++u) {
+            if (h[u]) lo = min(lo, h[u]);
+            hi = max(hi, h[u]);
+        }
+        // wave-wide min of lo and max of hi
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            lo = min(lo, (uint32_t)__shfl_xor((int)lo, m, 64));
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, m, 64));
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        hi = __builtin_amdgcn_readfirstlane(hi);
+        // invariant: count(h >= lo) >= kRound; the answer lies in [lo, hi]
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo + 1) / 2;
+            if (count_at_least(h, mid) >= kRound)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        T = lo;
+    }
+    const int C = count_at_least(h, T);
+    if (C <= 2 * kRound) {
+        int base = 0;
+#pragma unroll
+        for (int u = 0; u < kSel; ++u) {
+            const bool sel = h[u] >= T;
+            const unsigned long long m = __ballot(sel);
+            if (sel) buf[base + __popcll(m & ((1ull << lane) - 1))] = key[u];
+            base += __popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const u64 a = lane < C ? buf[lane] : 0;
+        const u64 b = lane + 64 < C ? buf[lane + 64] : 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // buf may be reused by the caller
+        return wave_merge_top(wave_sort_desc(a, lane), wave_sort_desc(b, lane), lane);
+    }
+    u64 list = 0;
+#pragma unroll
+    for (int u = 0; u < kSel; ++u) {
+        const u64 k = h[u] >= T ? key[u] : 0;
+        if (__ballot(k != 0)) list = wave_merge_top(list, wave_sort_desc(k, lane), lane);
+    }
+    return list;
+}
+
 struct TopkParams {
     const int32_t *A;
     const uint32_t *taken;  // bitmap of jobs taken before this round
@@ -69,6 +152,7 @@ struct TopkParams {
 
 __global__ __launch_bounds__(kTopkBlock) void k_greedy_topk(TopkParams P) {
     __shared__ u64 wl[kTopkWaves][64];
+    __shared__ u64 cand[kTopkWaves][2 * 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row = P.row0 + blockIdx.x;
     const int32_t *Ar = P.A + (int64_t)row * P.n;
@@ -76,43 +160,49 @@ __global__ __launch_bounds__(kTopkBlock) void k_greedy_topk(TopkParams P) {
     const int sub = ((P.n + kTopkWaves * 64 - 1) / (kTopkWaves * 64)) * 64;  // columns per wave
     const int c0 = w * sub;
     const int c1 = min(P.n, c0 + sub);
-    u64 list = 0, lmin = 0;
-    constexpr int U = 8;  // batches loaded ahead
-    for (int g0 = c0; g0 < c1; g0 += 64 * U) {
-        int val[U];
-        bool ok[U];
+    u64 list = 0;
+    if (sub <= 64 * kSel) {
+        list = wave_top_select(Ar, P.taken, c0, c1, lane, cand[w]);
+    } else {
+        // streaming: batches of 64 keys, sorted and merged when many pass the running bound
+        u64 lmin = 0;
+        constexpr int U = 8;  // batches loaded ahead
+        for (int g0 = c0; g0 < c1; g0 += 64 * U) {
+            int val[U];
+            bool ok[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = g0 + u * 64 + lane;
-            ok[u] = false;
-            val[u] = 0;
-            if (c < c1) {
-                ok[u] = !((P.taken[c >> 5] >> (c & 31)) & 1u);
-                val[u] = Ar[c];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = g0 + u * 64 + lane;
-            u64 key = ok[u] ? mk_key(val[u], c) : 0;
-            if (key <= lmin) key = 0;
-            const unsigned long long m = __ballot(key != 0);
-            if (m == 0) continue;
-            if (__popcll(m) > 8) {
-                list = wave_merge_top(list, wave_sort_desc(key, lane), lane);
-            } else {
-                unsigned long long mm = m;
-                while (mm) {
-                    const int src = __ffsll((long long)mm) - 1;
-                    mm &= mm - 1;
-                    const u64 k = readlane64(key, src);
-                    // insert k into the descending list: lanes below k shift down by one
-                    const u64 up = ((u64)(uint32_t)__shfl_up((int)(uint32_t)(list >> 32), 1, 64) << 32) |
-                                   (u64)(uint32_t)__shfl_up((int)(uint32_t)list, 1, 64);
-                    if (list < k) list = (lane == 0 || up > k) ? k : up;
+            for (int u = 0; u < U; ++u) {
+                const int c = g0 + u * 64 + lane;
+                ok[u] = false;
+                val[u] = 0;
+                if (c < c1) {
+                    ok[u] = !((P.taken[c >> 5] >> (c & 31)) & 1u);
+                    val[u] = Ar[c];
                 }
             }
-            lmin = readlane64(list, 63);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = g0 + u * 64 + lane;
+                u64 key = ok[u] ? mk_key(val[u], c) : 0;
+                if (key <= lmin) key = 0;
+                const unsigned long long m = __ballot(key != 0);
+                if (m == 0) continue;
+                if (__popcll(m) > 8) {
+                    list = wave_merge_top(list, wave_sort_desc(key, lane), lane);
+                } else {
+                    unsigned long long mm = m;
+                    while (mm) {
+                        const int src = __ffsll((long long)mm) - 1;
+                        mm &= mm - 1;
+                        const u64 k = readlane64(key, src);
+                        // insert k into the descending list: lanes below k shift down by one
+                        const u64 up = ((u64)(uint32_t)__shfl_up((int)(uint32_t)(list >> 32), 1, 64) << 32) |
+                                       (u64)(uint32_t)__shfl_up((int)(uint32_t)list, 1, 64);
+                        if (list < k) list = (lane == 0 || up > k) ? k : up;
+                    }
+                }
+                lmin = readlane64(list, 63);
+            }
         }
     }
     // pairwise merges of the wave lists: after the step of span s, wave w (w % 2s == 0)
