@@ -114,25 +114,36 @@ __device__ __forceinline__ void linsert(u64 *L, u64 &B, u64 y) {
 
 // Full evaluation of agent r by one wave (row of A staged in `arow`).
 // Returns top-2 keys (gain, job) over partners c != r in lane 0..63 (all lanes).
+// Both rows are loaded with every load in flight at once (one memory round
+// trip per agent).
 __device__ __forceinline__ void wave_eval_row(const int32_t *A, const int32_t *AT, int n, int r,
                                               const uint16_t *rt, const int32_t *rd, int32_t *arow, u64 &b1,
                                               u64 &b2) {
+    constexpr int kPer = kBatchMaxN / 64;
     const int lane = threadIdx.x & 63;
     const int32_t *Ar = A + (int64_t)r * n;
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // earlier reads of arow are done
-    for (int c = lane; c < n; c += 64) arow[c] = Ar[c];
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the row is in LDS for every lane
     const int32_t *Tr = AT + (int64_t)rt[r] * n;
+    int av[kPer], tv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int c = lane + 64 * u;
+        av[u] = c < n ? Ar[c] : 0;
+        tv[u] = c < n ? Tr[c] : 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // earlier reads of arow are done
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int c = lane + 64 * u;
+        if (c < n) arow[c] = av[u];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the row is in LDS for every lane
     const int dr = rd[r];
     b1 = 0;
     b2 = 0;
-    int g2 = INT32_MIN;
-    for (int c = lane; c < n; c += 64) {
-        const int g = (arow[rt[c]] + Tr[c]) - (dr + rd[c]);
-        if (g >= g2 && c != r) {
-            top2_push(b1, b2, mk_key(g, rt[c]));
-            g2 = b2 ? key_gain(b2) : INT32_MIN;
-        }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int c = lane + 64 * u;
+        if (c < n && c != r) top2_push(b1, b2, mk_key((arow[rt[c]] + tv[u]) - (dr + rd[c]), rt[c]));
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) top2_merge(b1, b2, shfl_xor64(b1, m), shfl_xor64(b2, m));
@@ -235,12 +246,17 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
                 const int bi = tt / nt, bj = tt % nt;
                 // two passes of 32 rows (a 64 x 32 tile with padding fits the wave's buffer)
                 for (int h = 0; h < 2; ++h) {
+                    int v[32];  // the 32 rows' loads all in flight at once
+#pragma unroll
                     for (int rr = 0; rr < 32; ++rr) {
                         const int row = bi * 64 + h * 32 + rr, col = bj * 64 + lane;
-                        tile[rr * 65 + lane] = (row < n && col < n) ? A[(int64_t)row * n + col] : 0;
+                        v[rr] = (row < n && col < n) ? A[(int64_t)row * n + col] : 0;
                     }
+#pragma unroll
+                    for (int rr = 0; rr < 32; ++rr) tile[rr * 65 + lane] = v[rr];
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                     // AT[col][row] for col = bj*64 + cc, row = bi*64 + h*32 + lane (lane < 32)
+#pragma unroll 8
                     for (int cc = 0; cc < 64; ++cc) {
                         const int col = bj * 64 + cc, row = bi * 64 + h * 32 + lane;
                         if (lane < 32 && col < n && row < n) I.AT[(int64_t)col * n + row] = tile[lane * 65 + cc];
