@@ -183,46 +183,52 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
         for (int u = 0; u < RPT; ++u) taken[u] = false;
         int bad = 0;
         int64_t f0 = 0;
-        int nv[RPT];
+        // rows are loaded kAhead agents ahead, every load unconditional (clamped addresses,
+        // values outside the instance unused) so that each wait covers exactly one row
+        constexpr int kAhead = 4;
+        int nv[kAhead][RPT];
 #pragma unroll
-        for (int u = 0; u < RPT; ++u) {
-            const int c = t + u * BLOCK;
-            nv[u] = c < n ? A[c] : 0;
+        for (int d = 0; d < kAhead; ++d) {
+            const int32_t *Ar = A + (int64_t)min(d, n - 1) * n;
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) nv[d][u] = Ar[min(t + u * BLOCK, n - 1)];
         }
-        for (int i = 0; i < n; ++i) {
-            int v[RPT];
+        for (int i0 = 0; i0 < n; i0 += kAhead) {
 #pragma unroll
-            for (int u = 0; u < RPT; ++u) v[u] = nv[u];
-            if (i + 1 < n) {
-                const int32_t *Ar = A + (int64_t)(i + 1) * n;
+            for (int d = 0; d < kAhead; ++d) {
+                const int i = i0 + d;
+                if (i >= n) break;
+                int v[RPT];
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) v[u] = nv[d][u];
+                {
+                    const int32_t *Ar = A + (int64_t)min(i + kAhead, n - 1) * n;
+#pragma unroll
+                    for (int u = 0; u < RPT; ++u) nv[d][u] = Ar[min(t + u * BLOCK, n - 1)];
+                }
+                u64 best = 0;
 #pragma unroll
                 for (int u = 0; u < RPT; ++u) {
                     const int c = t + u * BLOCK;
-                    nv[u] = c < n ? Ar[c] : 0;
+                    if (c < n) {
+                        bad |= (v[u] > kMaxAbsB) | (v[u] < -kMaxAbsB);
+                        if (!taken[u]) best = umax64(best, mk_key(v[u], c));
+                    }
                 }
-            }
-            u64 best = 0;
+                best = bmax1<BLOCK>(best, red, slot);
+                const int c = best ? key_index(best) : 0;  // a free column always exists
+                if (c % BLOCK == t) {
 #pragma unroll
-            for (int u = 0; u < RPT; ++u) {
-                const int c = t + u * BLOCK;
-                if (c < n) {
-                    bad |= (v[u] > kMaxAbsB) | (v[u] < -kMaxAbsB);
-                    if (!taken[u]) best = umax64(best, mk_key(v[u], c));
+                    for (int u = 0; u < RPT; ++u)
+                        if (u == c / BLOCK) taken[u] = true;
                 }
+                if (t == 0) {
+                    rt[i] = (uint16_t)c;
+                    rs[c] = (uint16_t)i;
+                    rd[i] = key_gain(best);
+                }
+                f0 += key_gain(best);
             }
-            best = bmax1<BLOCK>(best, red, slot);
-            const int c = best ? key_index(best) : 0;  // a free column always exists
-            if (c % BLOCK == t) {
-#pragma unroll
-                for (int u = 0; u < RPT; ++u)
-                    if (u == c / BLOCK) taken[u] = true;
-            }
-            if (t == 0) {
-                rt[i] = (uint16_t)c;
-                rs[c] = (uint16_t)i;
-                rd[i] = key_gain(best);
-            }
-            f0 += key_gain(best);
         }
         {
             u64 b = bad ? 1 : 0;
