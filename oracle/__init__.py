@@ -13,6 +13,8 @@ Contents:
     DGS with exact incremental re-evaluation, and an O(n^3) Hungarian
     optimum.  Built by ``oracle/build.py`` into ``liboracle.so`` and
     wrapped below with ctypes.
+  * ``parallel_dgs`` (below) -- Algorithm 3 with Check Conflicts
+    (Algorithm 4), rounds of the C scan and an index-order claim walk.
 
 Every function computes in int64.  Parity unpinned: none -- each function
 is pinned by the tests listed in the repository's design notes.
@@ -129,6 +131,39 @@ def dgs_full(A, init=None, max_switches=-1, trace_cap=0):
 def dgs_incr(A, init=None, max_switches=-1, trace_cap=0):
     """DGS with exact incremental re-evaluation (same result as dgs_full)."""
     return _run(lib().orc_dgs_incr, A, init, max_switches, trace_cap, True)
+
+
+def parallel_dgs(A, init=None, max_rounds=-1):
+    """Algorithm 3 with Check Conflicts (Algorithm 4), ADE only: each round
+    evaluates every agent afresh (the C scan), walks the agents with a positive
+    best exchange in index order, accepts agent i unless i or i' = sigma(j_i)
+    (the current owner of i's best job) is claimed by an accepted agent before
+    it, and applies all accepted exchanges (they are disjoint, so each gain is
+    exact and f grows by their sum).  Stops when no agent has a positive best.
+    Returns dict(tau, f, S = switches applied, rounds)."""
+    A = _mat(A)
+    n = A.shape[0]
+    tau = greedy(A) if init is None else np.array(init, dtype=np.int32, copy=True)
+    S = rounds = 0
+    while max_rounds < 0 or rounds < max_rounds:
+        g, j = scan(A, tau)
+        sigma = np.empty(n, dtype=np.int32)
+        sigma[tau] = np.arange(n, dtype=np.int32)
+        claimed = np.zeros(n, dtype=bool)
+        acc = []
+        for i in np.flatnonzero(g > 0):
+            ip = int(sigma[j[i]])
+            if claimed[i] or claimed[ip]:
+                continue
+            claimed[i] = claimed[ip] = True
+            acc.append((int(i), ip))
+        if not acc:
+            break
+        for i, ip in acc:
+            tau[i], tau[ip] = tau[ip], tau[i]
+        S += len(acc)
+        rounds += 1
+    return dict(tau=tau, f=objective(A, tau), S=S, rounds=rounds)
 
 
 def hungarian(A):

@@ -97,3 +97,41 @@ def dgs(A, init=None, max_switches=-1):
         tau = switch(bi, rb[bi][1], tau)
         S += 1
     return tau, objective(A, tau), S, trace
+
+
+def check_conflicts(rb, tau):
+    """Algorithm 4 (Check Conflicts), ADE part, read in index order: agent i with a
+    positive best (g_i, j_i) claims itself and i' = sigma(j_i), the current owner of
+    j_i, unless one of the two is claimed already (then i is in the conflict set).
+    Returns (accepted agents, conflict set)."""
+    sigma = inverse(tau)
+    claimed = set()
+    accepted, conflicts = [], []
+    for i, (g, j) in enumerate(rb):
+        if g is None or g <= 0:
+            continue
+        ip = sigma[j]
+        if i in claimed or ip in claimed:
+            conflicts.append(i)
+        else:
+            claimed.update((i, ip))
+            accepted.append(i)
+    return accepted, conflicts
+
+
+def parallel_dgs(A, init=None, max_rounds=-1):
+    """Algorithm 3 (parallel DGS): every round evaluates all agents afresh, keeps
+    the non-conflicting positive exchanges (Algorithm 4) and applies them all.
+    Returns (tau, f, switches, rounds)."""
+    tau = list(greedy(A) if init is None else init)
+    S = rounds = 0
+    while max_rounds < 0 or rounds < max_rounds:
+        rb = scan(A, tau)
+        accepted, _ = check_conflicts(rb, tau)
+        if not accepted:
+            break
+        for i in accepted:  # disjoint pairs: the order does not matter
+            tau = switch(i, rb[i][1], tau)
+        S += len(accepted)
+        rounds += 1
+    return tau, objective(A, tau), S, rounds

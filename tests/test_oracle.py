@@ -236,3 +236,79 @@ def test_objective_accounting():
     assert r["f"] == f0 + int(r["trace"][2].sum())
     assert (r["trace"][2] > 0).all()
     assert r["f"] <= oracle.hungarian(A)[0]
+
+
+# ---- Parallel DGS (Algorithm 3 with Check Conflicts, Algorithm 4) ----------------------
+# Worked by hand (identity start, every diagonal entry 10): agent 0's best exchange is
+# with agent 1 (gain 1), agents 1 and 2 are each other's best (gain 10), agent 3 has no
+# positive exchange.  Index order accepts agent 0 first (claiming 0 and 1); agents 1 and
+# 2 conflict.  After (0, 1) the round-2 gains are all <= 0, so parallel DGS stops at
+# tau = [1, 0, 2, 3], f = 41, one switch in one round; steepest ascent instead takes the
+# gain-10 exchange (1, 2) and ends at f = 50.
+PAR_A = [[10, 11, 5, 0],
+         [10, 10, 15, 0],
+         [5, 15, 10, 0],
+         [0, 0, 0, 10]]
+
+
+def test_parallel_worked_example():
+    ident = [0, 1, 2, 3]
+    r = oracle.parallel_dgs(np.array(PAR_A), init=ident)
+    assert list(r["tau"]) == [1, 0, 2, 3] and r["f"] == 41 and r["S"] == 1 and r["rounds"] == 1
+    assert dgs_ref.parallel_dgs(PAR_A, init=ident) == ([1, 0, 2, 3], 41, 1, 1)
+    assert oracle.dgs_full(np.array(PAR_A), init=ident)["f"] == 50
+    acc, conf = dgs_ref.check_conflicts(dgs_ref.scan(PAR_A, ident), ident)
+    assert acc == [0] and conf == [1, 2]
+
+
+@pytest.mark.parametrize("name", ["2x2", "3x3 tie-break"])
+def test_parallel_on_single_switch_examples(name):
+    # one positive exchange per round: parallel DGS takes the same switches as DGS
+    A = np.array({"2x2": [[5, 4], [4, 1]], "3x3 tie-break": [[9, 8, 8], [8, 1, 0], [8, 0, 1]]}[name])
+    r, d = oracle.parallel_dgs(A), oracle.dgs_full(A)
+    assert list(r["tau"]) == list(d["tau"]) and r["f"] == d["f"] and r["S"] == d["S"] == r["rounds"]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_parallel_properties_small(seed):
+    """Against the definitions: every round's accepted exchanges are disjoint and
+    positive, f grows by exactly their sum, the end is a 2-swap local optimum, the
+    C-scan version equals the definitional one, and f <= the brute-force optimum."""
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 8))
+    A = rng.integers(-20, 20 if seed % 2 else 3, (n, n))
+    tau = list(dgs_ref.greedy(A.tolist()))
+    f = dgs_ref.objective(A.tolist(), tau)
+    rounds = S = 0
+    while True:
+        rb = dgs_ref.scan(A.tolist(), tau)
+        acc, conf = dgs_ref.check_conflicts(rb, tau)
+        if not acc:
+            assert all(g is None or g <= 0 for g, _ in rb)
+            break
+        sigma = dgs_ref.inverse(tau)
+        pairs = [(i, sigma[rb[i][1]]) for i in acc]
+        used = [x for p in pairs for x in p]
+        assert len(used) == len(set(used))  # disjoint
+        gain = sum(rb[i][0] for i in acc)
+        assert gain > 0
+        for i in acc:
+            tau = dgs_ref.switch(i, rb[i][1], tau)
+        assert dgs_ref.objective(A.tolist(), tau) == f + gain
+        f += gain
+        rounds += 1
+        S += len(acc)
+    r = oracle.parallel_dgs(A)
+    assert list(r["tau"]) == tau and r["f"] == f and r["S"] == S and r["rounds"] == rounds
+    assert r["f"] <= brute.optimum(A)[0]
+
+
+def test_parallel_prefix_and_resume():
+    A = gen.uniform_matrix(300, 0, 1000, 3)
+    full = oracle.parallel_dgs(A)
+    part = oracle.parallel_dgs(A, max_rounds=2)
+    rest = oracle.parallel_dgs(A, init=part["tau"])
+    assert part["rounds"] == 2 and rest["rounds"] == full["rounds"] - 2
+    assert list(rest["tau"]) == list(full["tau"]) and rest["f"] == full["f"]
+    g, _ = oracle.scan(A, full["tau"])
+    assert g.max() <= 0
