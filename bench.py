@@ -195,6 +195,31 @@ def run_single(args, dgs, torch, gen, np) -> dict:
     return line
 
 
+def run_parallel(args, dgs, torch, gen, np, steps: int = 3) -> dict:
+    """Parallel DGS (Algorithm 3 with Check Conflicts) on the same instance:
+    every round applies all non-conflicting improving exchanges at once.
+    A different trajectory from the steepest-ascent solve, so its own
+    objective and switch count; reported beside the headline line."""
+    A = gen.single_instance(args.workload, args.seed)
+    Ad = torch.from_numpy(A).to(torch.device("cuda:0"))
+    _, res = dgs.solve(Ad, profile=True, parallel=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        _, res = dgs.solve(Ad, profile=True, parallel=True)
+        results.append(res)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r = results[-1]
+    out = {"ms_per_solve": round(1000.0 * wall / steps, 3), "instances_per_s": round(steps / wall, 3),
+           "rounds": r["rounds"], "switches": r["switches"], "initial_benefit": r["initial_benefit"],
+           "total_benefit": r["total_benefit"],
+           "phase_ms": {p: round(float(np.mean([x["phase_ms"][p] for x in results])), 4) for p in dgs.PHASES}}
+    del Ad
+    return out
+
+
 def run_batched(args, dgs, torch, gen, np, steps: int, warmup: int, count: int = 512) -> dict:
     """The batched workload: `count` instances, n log-uniform in [64, 2048],
     iid uniform benefits in [0, 10000), solved by one graph-captured
@@ -347,6 +372,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="single-instance workloads: skip the batched summary")
+    ap.add_argument("--no-parallel", action="store_true",
+                    help="single-instance workloads: skip the Parallel DGS summary")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches): the reference "
@@ -379,6 +406,10 @@ def main() -> int:
 
     if args.workload in SINGLE:
         line = run_single(args, dgs, torch, gen, np)
+        if not args.no_parallel:
+            log("parallel DGS summary")
+            line["parallel"] = run_parallel(args, dgs, torch, gen, np)
+            log(f"parallel DGS: {line['parallel']}")
         if not args.no_batched:
             log("batched workload summary")
             line["batched"] = run_batched(args, dgs, torch, gen, np, steps=3, warmup=1)

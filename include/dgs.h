@@ -60,6 +60,16 @@ typedef enum dgs_status {
 #define DGS_DEVICE_PTRS 0x1u /* benefit, assign_out, init_assign are device pointers */
 #define DGS_PROFILE 0x2u     /* also time each phase with HIP events (dgs_result.phase_ms) */
 #define DGS_AUTOTUNE 0x4u    /* batch plans: pick the solver's workgroup size by timing it */
+/* dgs_solve_ex: Parallel DGS (Algorithm 3 with Check Conflicts, Algorithm 4)
+ * instead of the steepest-ascent switching loop.  Each round evaluates every
+ * agent afresh, walks the agents with a positive best exchange in index
+ * order, accepts agent i unless i or i' = sigma(j_i) (the current owner of
+ * i's best job j_i) was claimed by an agent accepted before it (an accepted
+ * agent claims both), and applies all accepted exchanges at once.  It stops
+ * when no agent has a positive best exchange; max_switches then bounds the
+ * number of ROUNDS (< 0: no bound).  Ends at a 2-exchange local optimum like
+ * the default mode, by another trajectory.  n <= 262144. */
+#define DGS_PARALLEL 0x8u
 
 /* dgs_result.phase_ms indices (filled only with DGS_PROFILE) */
 #define DGS_PHASE_RANGE 0  /* value-range check of the benefit matrix */
@@ -92,6 +102,7 @@ typedef struct dgs_result {
     int64_t stalls;          /* switching rounds that applied no switch (waited for a re-evaluation) */
     float device_ms;         /* device time of the solve (HIP events) */
     float phase_ms[DGS_NUM_PHASES]; /* per-phase device time (DGS_PROFILE only, else 0) */
+    int64_t rounds;          /* DGS_PARALLEL: rounds that applied at least one exchange (else 0) */
 } dgs_result;
 
 /* Solve one instance with default options (greedy start, run to the end).

@@ -105,7 +105,7 @@ std::multimap<int32_t, Workspace *> g_ws_free;
 // 256-byte boundary; vec_layout() is the single source of the offsets used
 // both to size the allocation and to carve it.
 struct VecLayout {
-    size_t tau, sigma, d, bc, bk, bb, lists, recs, barrier, stats, flags, words, greedy, scan, total;
+    size_t tau, sigma, d, bc, bk, bb, lists, recs, barrier, stats, flags, words, greedy, scan, par, total;
 };
 
 VecLayout vec_layout(int32_t n, int grid) {
@@ -131,6 +131,7 @@ VecLayout vec_layout(int32_t n, int grid) {
     L.words = take(ex ? switch_v3_word_bytes(n) : 0);
     L.greedy = take(greedy_scratch_bytes(n));
     L.scan = take(scan_pairs_scratch_bytes(n));
+    L.par = take((size_t)n * 4);
     L.total = off;
     return L;
 }
@@ -218,6 +219,7 @@ Instance carve(Workspace *w, const int32_t *A, int32_t n, int grid) {
     I.words = p + L.words;
     I.greedy = p + L.greedy;
     I.scan = p + L.scan;
+    I.par = (int32_t *)(p + L.par);
     return I;
 }
 
@@ -257,8 +259,30 @@ struct Call {
     bool dev;
     bool profile;
     bool coop = true;  // cooperative switching launch (else the caller owns co-residency)
+    bool parallel = false;  // Parallel DGS rounds instead of the switching loop (max_switches = max rounds)
     hipStream_t stream;
 };
+
+// Parallel DGS (Algorithm 3): rounds of Check Conflicts + apply, each
+// followed by a fresh difference evaluation, until a round accepts nothing.
+// Expects the evaluation of the start assignment in I.bk / I.bc.
+dgs_status parallel_rounds(const Instance &I, Workspace *w, int64_t max_rounds, int64_t *rounds_out, hipStream_t s) {
+    int64_t rounds = 0;
+    int64_t *accepted = w->host_stats + 12;
+    while (max_rounds < 0 || rounds < max_rounds) {
+        DGS_HIP(launch_parallel_round(I, I.par, s));
+        DGS_HIP(hipMemcpyAsync(accepted, I.stats + 5, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        DGS_HIP(hipStreamSynchronize(s));
+        if (*accepted == 0) break;
+        ++rounds;
+        if (max_rounds >= 0 && rounds >= max_rounds) break;
+        // stats[6] takes the objective sum of the rebuild (f0 stays the start's)
+        DGS_HIP(launch_build_w(I.A, I.AT, I.tau, I.n, I.W, I.d, I.stats + 6, s));
+        DGS_HIP(launch_scan_pairs(I, I.scan, s));
+    }
+    *rounds_out = rounds;
+    return DGS_OK;
+}
 
 // The whole device pipeline of one instance.
 dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *gain_out, int32_t *job_out,
@@ -277,6 +301,10 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         ~Guard() { release_ws(w); }
     } guard{w};
 
+    if (c.parallel && n > parallel_max_agents()) {
+        set_error("parallel mode supports n <= %d", parallel_max_agents());
+        return DGS_E_INVAL;
+    }
     const int grid = std::max(1, std::min(g_ctx.loop_grid, (int)n));
     if (vec_layout(n, grid).total > w->vec_bytes) {
         set_error("internal: workspace too small for n=%d", n);
@@ -308,7 +336,11 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     DGS_HIP(mark(DGS_PHASE_SCAN));
     DGS_HIP(launch_scan_pairs(I, I.scan, s));
     DGS_HIP(mark(DGS_PHASE_SWITCH));
-    if (mode == Mode::Solve) {
+    int64_t rounds = 0;
+    if (mode == Mode::Solve && c.parallel) {
+        st = parallel_rounds(I, w, c.max_switches, &rounds, s);
+        if (st != DGS_OK) return st;
+    } else if (mode == Mode::Solve) {
         // The loops exit at once when the range check failed.  n = 1 has no
         // exchange at all.  Cooperative switching loops of concurrent calls
         // run one at a time (each needs its whole grid resident).
@@ -360,6 +392,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         res->switches = hs[0];
         res->rescans = hs[3];
         res->stalls = hs[4];
+        res->rounds = rounds;
         res->device_ms = ms;
         for (int i = 0; i < DGS_NUM_PHASES; ++i) {
             float pm = 0.f;
@@ -672,6 +705,7 @@ dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out, 
     c.max_switches = opt ? opt->max_switches : -1;
     c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
     c.profile = opt && (opt->flags & DGS_PROFILE);
+    c.parallel = opt && (opt->flags & DGS_PARALLEL);
     c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
     return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
 }

@@ -40,12 +40,14 @@ struct Instance {
     // scratch for the switch loop and small reductions
     void *recs = nullptr;        // 2 x grid records
     uint32_t *barrier = nullptr; // grid barrier counter
-    int64_t *stats = nullptr;    // [0] switches, [1] gain sum, [2] f0, [3] re-evaluations, [4] stalls
+    int64_t *stats = nullptr;    // [0] switches, [1] gain sum, [2] f0, [3] re-evaluations, [4] stalls,
+                                 // [5] accepted in the last parallel round, [6] scratch sum
     int32_t *flags = nullptr;    // [0] range error, [1] permutation error, [2] wait timed out
     void *words = nullptr;       // exchange words of the switching loop
     void *greedy = nullptr;      // scratch of the greedy start
     void *scan = nullptr;        // scratch of the difference evaluation (per-block top-2)
     u64 *lists = nullptr;        // [n][kScanListLen] initial candidate lists (keys, 0 = empty)
+    int32_t *par = nullptr;      // [n] Parallel DGS: partner of each accepted agent, else -1
 };
 
 // Host-side helpers of the C ABI (dgs_api.cpp).
@@ -118,6 +120,12 @@ struct BatchItem {
 hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
                         int64_t max_switches, int block, int grid, hipStream_t s);
 int batch_grid_limit(int block);
+
+// Parallel DGS (dgs_parallel.hip): one round of Check Conflicts over the
+// fresh bests in I.bk / I.bc (accepted partners into acc, stats[0] and [1]
+// advanced, stats[5] = accepted count) followed by the swaps.
+int parallel_max_agents();
+hipError_t launch_parallel_round(const Instance &I, int32_t *acc, hipStream_t s);
 
 hipError_t launch_export_best(const Instance &I, int64_t *gain_out, int32_t *job_out,
                               hipStream_t s);

@@ -12,6 +12,10 @@ With ``--prefix`` it writes tests/golden/lowrank20480_prefix.txt instead:
 the oracle's state after the first 1000 switches of the n = 20480 instance
 (seed 1), a size whose switching launch gathers more than 8 exchange words
 per thread.
+
+With ``--parallel`` it writes tests/golden/lowrank16384_parallel.txt: the
+oracle's Parallel DGS (Algorithm 3 with Check Conflicts) from the greedy
+start of the n = 16384 workload, seeds 1 and 2.
 """
 from __future__ import annotations
 
@@ -31,6 +35,7 @@ from workloads import gen  # noqa: E402
 OUT = os.path.join(HERE, "lowrank16384.txt")
 OUT_PREFIX = os.path.join(HERE, "lowrank20480_prefix.txt")
 PREFIX_N, PREFIX_K = 20480, 1000
+OUT_PARALLEL = os.path.join(HERE, "lowrank16384_parallel.txt")
 
 
 def main(seeds):
@@ -69,8 +74,30 @@ def prefix(seed=1):
     print(f"prefix seed {seed}: S={r['S']} f={r['f']} ({time.time() - t0:.0f} s)", flush=True)
 
 
+def parallel(seeds=(1, 2)):
+    lines = ["# Oracle Parallel DGS (Algorithm 3 with Check Conflicts, Algorithm 4) on the",
+             "# n = 16384 low-rank-plus-noise workload (workloads.gen.lowrank_matrix(16384, seed)),",
+             "# greedy start, run until no agent has an improving exchange; written by",
+             "# make_golden.py --parallel.  tau_sha256 as in lowrank16384.txt."]
+    for seed in seeds:
+        t0 = time.time()
+        A = gen.lowrank_matrix(16384, seed)
+        g = oracle.greedy(A)
+        r = oracle.parallel_dgs(A, init=g)
+        h = hashlib.sha256(np.ascontiguousarray(r["tau"], dtype="<i4").tobytes()).hexdigest()
+        lines += ["", f"[seed{seed}]", f"greedy_f = {oracle.objective(A, g)}", f"f = {r['f']}",
+                  f"S = {r['S']}", f"rounds = {r['rounds']}", f"tau_sha256 = {h}"]
+        print(f"parallel seed {seed}: S={r['S']} rounds={r['rounds']} f={r['f']} ({time.time() - t0:.0f} s)",
+              flush=True)
+        del A
+    with open(OUT_PARALLEL, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1:2] == ["--prefix"]:
         prefix()
+    elif sys.argv[1:2] == ["--parallel"]:
+        parallel()
     else:
         main([int(s) for s in sys.argv[1:]] or [1, 2, 3, 4, 5])

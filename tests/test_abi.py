@@ -61,3 +61,14 @@ def test_product_does_not_reference_the_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in src.lower(), f
+
+
+def test_binding_flags_and_result_fields_match_header():
+    import paper_1106_5694_amd as dgs
+    text = open(HEADER).read()
+    for name, val in re.findall(r"#define (DGS_[A-Z_]+) (0x[0-9a-fA-F]+)u", text):
+        assert getattr(dgs, name) == int(val, 16), name
+    body = re.search(r"typedef struct dgs_result \{(.*?)\} dgs_result;", text, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b([a-z_]+)(?:\[[A-Z_]+\])?;", body)
+    assert fields == [f for f, _ in dgs.Result._fields_]
