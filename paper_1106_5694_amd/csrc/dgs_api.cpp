@@ -265,7 +265,8 @@ struct Call {
 
 // Parallel DGS (Algorithm 3): rounds of Check Conflicts + apply, each
 // followed by a fresh difference evaluation, until a round accepts nothing.
-// Expects the evaluation of the start assignment in I.bk / I.bc.
+// Expects the evaluation of the start assignment in I.bk / I.bc.  The
+// evaluations read A^T through tau, so W is never built.
 dgs_status parallel_rounds(const Instance &I, Workspace *w, int64_t max_rounds, int64_t *rounds_out, hipStream_t s) {
     int64_t rounds = 0;
     int64_t *accepted = w->host_stats + 12;
@@ -276,9 +277,9 @@ dgs_status parallel_rounds(const Instance &I, Workspace *w, int64_t max_rounds, 
         if (*accepted == 0) break;
         ++rounds;
         if (max_rounds >= 0 && rounds >= max_rounds) break;
-        // stats[6] takes the objective sum of the rebuild (f0 stays the start's)
-        DGS_HIP(launch_build_w(I.A, I.AT, I.tau, I.n, I.W, I.d, I.stats + 6, s));
-        DGS_HIP(launch_scan_pairs(I, I.scan, s));
+        // fresh d and evaluation; stats[6] takes the objective sum (f0 stays the start's)
+        DGS_HIP(launch_benefits(I.A, I.tau, I.n, I.d, I.stats + 6, s));
+        DGS_HIP(launch_scan_pairs(I, I.scan, s, true));
     }
     *rounds_out = rounds;
     return DGS_OK;
@@ -332,9 +333,12 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     }
     DGS_HIP(mark(DGS_PHASE_LAYOUT));
     DGS_HIP(launch_transpose(A, I.AT, n, s));
-    DGS_HIP(launch_build_w(A, I.AT, I.tau, n, I.W, I.d, I.stats + 2, s));
+    if (c.parallel && mode == Mode::Solve)
+        DGS_HIP(launch_benefits(A, I.tau, n, I.d, I.stats + 2, s));
+    else
+        DGS_HIP(launch_build_w(A, I.AT, I.tau, n, I.W, I.d, I.stats + 2, s));
     DGS_HIP(mark(DGS_PHASE_SCAN));
-    DGS_HIP(launch_scan_pairs(I, I.scan, s));
+    DGS_HIP(launch_scan_pairs(I, I.scan, s, c.parallel && mode == Mode::Solve));
     DGS_HIP(mark(DGS_PHASE_SWITCH));
     int64_t rounds = 0;
     if (mode == Mode::Solve && c.parallel) {

@@ -82,10 +82,13 @@ hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t n, hipStream_
 // W from AT (built first) and tau; d and f0 from A.
 hipError_t launch_build_w(const int32_t *A, const int32_t *AT, const int32_t *tau, int32_t n, int32_t *W,
                           int32_t *d, int64_t *f0, hipStream_t s);
+// d and the objective sum alone (W left as it is).
+hipError_t launch_benefits(const int32_t *A, const int32_t *tau, int32_t n, int32_t *d, int64_t *f, hipStream_t s);
 hipError_t launch_scan_rows(const Instance &I, hipStream_t s);
 // Symmetric tile-pair difference evaluation (dgs_scan.hip).
 size_t scan_pairs_scratch_bytes(int n);
-hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s);
+// from_transpose: read A^T through tau instead of W (same results; W need not be built).
+hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s, bool from_transpose = false);
 hipError_t launch_switch_loop(const Instance &I, int64_t max_switches, int grid, hipStream_t s);
 // Largest n of the switching loop with cooperative re-evaluation (16-bit agent and job fields).
 constexpr int kSwitchExMaxN = 65535;

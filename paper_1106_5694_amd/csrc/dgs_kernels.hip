@@ -556,6 +556,12 @@ hipError_t launch_build_w(const int32_t *A, const int32_t *AT, const int32_t *ta
     return hipGetLastError();
 }
 
+hipError_t launch_benefits(const int32_t *A, const int32_t *tau, int32_t n, int32_t *d, int64_t *f, hipStream_t s) {
+    hipLaunchKernelGGL(k_benefits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, tau, n, d,
+                       (unsigned long long *)f);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan_rows(const Instance &I, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)I.n), dim3(256), 0, s, I.W, I.AT, I.tau, I.sigma, I.d,
                        I.n, I.bk, I.bb, I.bc);

@@ -10,6 +10,10 @@
 // a top-2 (best, second) per agent and per partner block; k_scan_reduce
 // merges an agent's blocks into its best exchange and the second best
 // (the bound of the candidate list).  Ties: larger gain, then lower job.
+//
+// g is symmetric in the two tiles, so the same scores come from V = W^T:
+// row x of V is row tau(x) of A^T (V[x][y] = a[y][tau(x)] = W[y][x]).  The
+// row-indirect variant reads the transpose through tau and needs no W.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -41,7 +45,8 @@ __device__ __forceinline__ void pair_of(long long p, int nb, int &I, int &K) {
 }
 
 struct ScanParams {
-    const int32_t *W;
+    const int32_t *W;     // W, or A^T for the row-indirect variant
+    const int32_t *rows;  // row-indirect variant: tile row x is row rows[x] of the matrix
     const int32_t *tau;
     const int32_t *d;
     u64 *part;  // [n][nb][2]
@@ -52,7 +57,7 @@ struct ScanParams {
 // One workgroup of BLOCK threads per tile pair: BLOCK / 64 threads per tile
 // row, each scoring 64 / (BLOCK / 64) partners on each side; interior pairs
 // (no bounds, no diagonal) take an unrolled path.
-template <int BLOCK>
+template <int BLOCK, bool kRows>
 __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     constexpr int Q = BLOCK / 64;  // threads per tile row
     constexpr int E = kTile / Q;   // partners per thread
@@ -66,14 +71,15 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     const int i0 = I * kTile, k0 = K * kTile;
     const int t = threadIdx.x;
     const bool full = (n % 4 == 0) && i0 + kTile <= n && k0 + kTile <= n;
+    auto row = [&](int x) { return P.W + (int64_t)(kRows ? P.rows[x] : x) * n; };
     if (full) {
         int4 va[LD], vb[LD];
 #pragma unroll
         for (int u = 0; u < LD; ++u) {
             const int e = t + u * BLOCK;
             const int r = e >> 4, c4 = (e & 15) * 4;
-            va[u] = *(const int4 *)(P.W + (int64_t)(i0 + r) * n + k0 + c4);
-            vb[u] = *(const int4 *)(P.W + (int64_t)(k0 + r) * n + i0 + c4);
+            va[u] = *(const int4 *)(row(i0 + r) + k0 + c4);
+            vb[u] = *(const int4 *)(row(k0 + r) + i0 + c4);
         }
 #pragma unroll
         for (int u = 0; u < LD; ++u) {
@@ -91,8 +97,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     } else {
         for (int e = t; e < kTile * kTile; e += BLOCK) {
             const int r = e >> 6, c = e & 63;
-            tA[r][c] = (i0 + r < n && k0 + c < n) ? P.W[(int64_t)(i0 + r) * n + k0 + c] : 0;
-            tB[r][c] = (k0 + r < n && i0 + c < n) ? P.W[(int64_t)(k0 + r) * n + i0 + c] : 0;
+            tA[r][c] = (i0 + r < n && k0 + c < n) ? row(i0 + r)[k0 + c] : 0;
+            tB[r][c] = (k0 + r < n && i0 + c < n) ? row(k0 + r)[i0 + c] : 0;
         }
     }
     if (t < kTile) {
@@ -225,11 +231,14 @@ size_t scan_pairs_scratch_bytes(int n) {
     return (size_t)n * nb * 2 * sizeof(u64);
 }
 
-hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s) {
+hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s, bool from_transpose) {
     const int nb = (I.n + kTile - 1) / kTile;
     const long long pairs = (long long)nb * (nb + 1) / 2;
-    ScanParams P{I.W, I.tau, I.d, (u64 *)scratch, I.n, nb};
-    hipLaunchKernelGGL(k_scan_pairs_b<kScanBlock>, dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    ScanParams P{from_transpose ? I.AT : I.W, I.tau, I.tau, I.d, (u64 *)scratch, I.n, nb};
+    if (from_transpose)
+        hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    else
+        hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
                        nb, I.sigma, I.bk, I.bb, I.bc, I.lists);
     return hipGetLastError();
