@@ -279,7 +279,7 @@ dgs_status parallel_rounds(const Instance &I, Workspace *w, int64_t max_rounds, 
         if (max_rounds >= 0 && rounds >= max_rounds) break;
         // fresh d and evaluation; stats[6] takes the objective sum (f0 stays the start's)
         DGS_HIP(launch_benefits(I.A, I.tau, I.n, I.d, I.stats + 6, s));
-        DGS_HIP(launch_scan_pairs(I, I.scan, s, true));
+        DGS_HIP(launch_scan_best_transposed(I, I.scan, s));
     }
     *rounds_out = rounds;
     return DGS_OK;
@@ -338,7 +338,10 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     else
         DGS_HIP(launch_build_w(A, I.AT, I.tau, n, I.W, I.d, I.stats + 2, s));
     DGS_HIP(mark(DGS_PHASE_SCAN));
-    DGS_HIP(launch_scan_pairs(I, I.scan, s, c.parallel && mode == Mode::Solve));
+    if (c.parallel && mode == Mode::Solve)
+        DGS_HIP(launch_scan_best_transposed(I, I.scan, s));
+    else
+        DGS_HIP(launch_scan_pairs(I, I.scan, s));
     DGS_HIP(mark(DGS_PHASE_SWITCH));
     int64_t rounds = 0;
     if (mode == Mode::Solve && c.parallel) {

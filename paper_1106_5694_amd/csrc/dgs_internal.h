@@ -87,8 +87,10 @@ hipError_t launch_benefits(const int32_t *A, const int32_t *tau, int32_t n, int3
 hipError_t launch_scan_rows(const Instance &I, hipStream_t s);
 // Symmetric tile-pair difference evaluation (dgs_scan.hip).
 size_t scan_pairs_scratch_bytes(int n);
-// from_transpose: read A^T through tau instead of W (same results; W need not be built).
-hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s, bool from_transpose = false);
+hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s);
+// The same evaluation read from A^T through tau (W need not be built), writing
+// only each agent's best (bk, bc): the per-round evaluation of Parallel DGS.
+hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s);
 hipError_t launch_switch_loop(const Instance &I, int64_t max_switches, int grid, hipStream_t s);
 // Largest n of the switching loop with cooperative re-evaluation (16-bit agent and job fields).
 constexpr int kSwitchExMaxN = 65535;

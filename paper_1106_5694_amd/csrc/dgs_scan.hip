@@ -157,6 +157,23 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     }
 }
 
+// One wave per agent: the best of its nb block bests (no list, no bound).
+__global__ __launch_bounds__(256) void k_scan_best(const u64 *__restrict__ part, int n, int nb,
+                                                    const int32_t *__restrict__ sigma, u64 *bk, int32_t *bc) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= n) return;
+    const u64 *p = part + (size_t)r * nb * 2;
+    u64 m = 0;
+    for (int x = lane; x < nb; x += 64) m = umax64(m, p[2 * x]);
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) m = umax64(m, shfl_xor64(m, s));
+    if (lane == 0) {
+        bk[r] = m;
+        bc[r] = m ? sigma[key_index(m)] : -1;
+    }
+}
+
 // One wave per agent: merge its nb block top-2s into the agent's candidate
 // list.  Every candidate that is not a block's best is <= its block's
 // second, so B = max over blocks of the second is a bound for everything
@@ -231,14 +248,21 @@ size_t scan_pairs_scratch_bytes(int n) {
     return (size_t)n * nb * 2 * sizeof(u64);
 }
 
-hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s, bool from_transpose) {
+hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s) {
     const int nb = (I.n + kTile - 1) / kTile;
     const long long pairs = (long long)nb * (nb + 1) / 2;
-    ScanParams P{from_transpose ? I.AT : I.W, I.tau, I.tau, I.d, (u64 *)scratch, I.n, nb};
-    if (from_transpose)
-        hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
-    else
-        hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    ScanParams P{I.AT, I.tau, I.tau, I.d, (u64 *)scratch, I.n, nb};
+    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    hipLaunchKernelGGL(k_scan_best, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
+                       nb, I.sigma, I.bk, I.bc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s) {
+    const int nb = (I.n + kTile - 1) / kTile;
+    const long long pairs = (long long)nb * (nb + 1) / 2;
+    ScanParams P{I.W, nullptr, I.tau, I.d, (u64 *)scratch, I.n, nb};
+    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
                        nb, I.sigma, I.bk, I.bb, I.bc, I.lists);
     return hipGetLastError();

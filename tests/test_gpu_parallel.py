@@ -153,3 +153,9 @@ def test_lowrank16384_golden(dgs, seed):
     assert res["total_benefit"] == int(gold["f"])
     assert res["switches"] == int(gold["S"]) and res["rounds"] == int(gold["rounds"])
     assert h == gold["tau_sha256"]
+
+
+def test_ordered_walk_above_16384(dgs):
+    # n > 16384 takes the single-wave ordered walk of Check Conflicts
+    # instead of the in-LDS iteration; both must give the oracle's result
+    check(dgs, gen.uniform_matrix(16400, 0, 100000, 5), what="uniform n=16400")
