@@ -15,6 +15,9 @@ Contents:
     wrapped below with ctypes.
   * ``parallel_dgs`` (below) -- Algorithm 3 with Check Conflicts
     (Algorithm 4), rounds of the C scan and an index-order claim walk.
+  * ``lazy_dgs`` (below) -- Algorithm 1 as printed (stale bests of agents
+    and jobs, the branch rule, the improvement guard, repeated passes),
+    with numpy row evaluations.
 
 Every function computes in int64.  Parity unpinned: none -- each function
 is pinned by the tests listed in the repository's design notes.
@@ -164,6 +167,87 @@ def parallel_dgs(A, init=None, max_rounds=-1):
         S += len(acc)
         rounds += 1
     return dict(tau=tau, f=objective(A, tau), S=S, rounds=rounds)
+
+
+def _ade_row(A, tau, sigma, i):
+    """Algorithm 2 for agent i: the best gain over jobs j != tau(i) of agent i
+    taking j (its owner sigma(j) taking tau(i)), lowest job on ties; stored
+    as (gain, job) when > 0, else (0, -1)."""
+    n = A.shape[0]
+    if n < 2:
+        return 0, -1
+    g = A[i, :] + A[sigma, tau[i]] - A[i, tau[i]] - A[sigma, np.arange(n)]
+    g[tau[i]] = NEG_INF
+    j = int(np.argmax(g))
+    return (int(g[j]), j) if g[j] > 0 else (0, -1)
+
+
+def _jde_row(A, tau, sigma, j):
+    """The job side: the best gain over agents i != sigma(j) of agent i taking
+    job j (sigma(j) taking tau(i)), lowest agent on ties; (gain, agent) when
+    > 0, else (0, -1)."""
+    n = A.shape[0]
+    if n < 2:
+        return 0, -1
+    o = sigma[j]
+    g = A[:, j] + A[o, tau] - A[np.arange(n), tau] - A[o, j]
+    g[o] = NEG_INF
+    i = int(np.argmax(g))
+    return (int(g[i]), i) if g[i] > 0 else (0, -1)
+
+
+def lazy_dgs(A, init=None, max_switches=-1):
+    """Algorithm 1 as printed.  Each pass evaluates every agent (ADE) and
+    every job (JDE) and stores their best positive improvements; then, while
+    a stored improvement is positive, it takes the agent i* and the job j*
+    with the largest stored values (lowest index on ties), follows i*'s
+    stored exchange if its value is strictly larger than j*'s, else j*'s,
+    zeroes the stored value it followed, and applies the exchange only if it
+    raises f, re-evaluating the two agents and the two jobs involved.
+    Passes repeat until one applies nothing; max_switches stops early.
+    Returns dict(tau, f, S = switches applied, attempts, passes)."""
+    A64 = _mat(A).astype(np.int64)
+    n = A64.shape[0]
+    tau = greedy(A) if init is None else np.array(init, dtype=np.int32, copy=True)
+    tau = tau.astype(np.int64)
+    S = attempts = passes = 0
+    while max_switches < 0 or S < max_switches:
+        passes += 1
+        sigma = np.empty(n, dtype=np.int64)
+        sigma[tau] = np.arange(n)
+        up = [_ade_row(A64, tau, sigma, i) for i in range(n)]
+        lo = [_jde_row(A64, tau, sigma, j) for j in range(n)]
+        dup = np.array([d for d, _ in up], dtype=np.int64)
+        dlo = np.array([d for d, _ in lo], dtype=np.int64)
+        applied = 0
+        while n > 1 and (dup.max() > 0 or dlo.max() > 0):
+            if 0 <= max_switches <= S:
+                break
+            attempts += 1
+            istar, jstar = int(np.argmax(dup)), int(np.argmax(dlo))
+            if dup[istar] > dlo[jstar]:
+                i, j = istar, up[istar][1]
+                dup[istar], up[istar] = 0, (0, -1)
+            else:
+                i, j = lo[jstar][1], jstar
+                dlo[jstar], lo[jstar] = 0, (0, -1)
+            k, t0 = int(sigma[j]), int(tau[i])
+            gain = A64[i, j] + A64[k, t0] - A64[i, t0] - A64[k, j]
+            if gain > 0:
+                tau[i], tau[k] = j, t0
+                sigma[j], sigma[t0] = i, k
+                S += 1
+                applied += 1
+                for x in (i, k):
+                    up[x] = _ade_row(A64, tau, sigma, x)
+                    dup[x] = up[x][0]
+                for y in (j, t0):
+                    lo[y] = _jde_row(A64, tau, sigma, y)
+                    dlo[y] = lo[y][0]
+        if applied == 0:
+            break
+    tau = tau.astype(np.int32)
+    return dict(tau=tau, f=objective(A, tau), S=S, attempts=attempts, passes=passes)
 
 
 def hungarian(A):

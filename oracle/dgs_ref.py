@@ -18,6 +18,12 @@ exactly) on many small random instances.
     gain is > 0, re-evaluate every agent, repeat
   * greedy start (Section 3.1): agents in index order take their best free
     job, lowest index on ties
+  * JDE (Section 3.3, job side of Algorithm 2): scan agents i' != sigma(j)
+    in index order, keep the first strictly better one
+  * lazy DGS (Algorithm 1 as printed): stale per-agent and per-job bests,
+    the paper's branch rule and improvement guard, re-evaluation of the two
+    agents and two jobs of an applied switch only, full passes repeated
+    until a pass applies nothing
 """
 from __future__ import annotations
 
@@ -135,3 +141,62 @@ def parallel_dgs(A, init=None, max_rounds=-1):
         S += len(accepted)
         rounds += 1
     return tau, objective(A, tau), S, rounds
+
+
+def best_positive(pair):
+    """Algorithm 2 keeps the start assignment unless a strictly better one
+    exists: the stored improvement is the best gain if > 0, else 0."""
+    g, x = pair
+    return (g, x) if g is not None and g > 0 else (0, -1)
+
+
+def jde(A, tau, j):
+    """(gain, agent) of job j's best 2-exchange: agent i' != sigma(j) takes j
+    (its old owner takes tau(i')); first strictly better agent in index order."""
+    f0 = objective(A, tau)
+    owner = inverse(tau)[j]
+    best, bi = NEG_INF, -1
+    for ip in range(len(tau)):
+        if ip == owner:
+            continue
+        g = objective(A, switch(ip, j, tau)) - f0
+        if best is None or g > best:
+            best, bi = g, ip
+    return best, bi
+
+
+def lazy_dgs(A, init=None, max_switches=-1):
+    """Algorithm 1 as printed.  Returns (tau, f, S, attempts, passes)."""
+    n = len(A)
+    tau = list(greedy(A) if init is None else init)
+    S = attempts = passes = 0
+    while max_switches < 0 or S < max_switches:
+        passes += 1
+        up = [best_positive(ade(A, tau, i)) for i in range(n)]   # (delta-bar_i, j_i)
+        lo = [best_positive(jde(A, tau, j)) for j in range(n)]   # (delta_j, i_j)
+        applied = 0
+        while max(d for d, _ in up) > 0 or max(d for d, _ in lo) > 0:
+            if 0 <= max_switches <= S:
+                break
+            attempts += 1
+            istar = max(range(n), key=lambda i: (up[i][0], -i))
+            jstar = max(range(n), key=lambda j: (lo[j][0], -j))
+            if up[istar][0] > lo[jstar][0]:
+                i, j = istar, up[istar][1]
+                up[istar] = (0, -1)
+            else:
+                i, j = lo[jstar][1], jstar
+                lo[jstar] = (0, -1)
+            k, t0 = inverse(tau)[j], tau[i]
+            new = switch(i, j, tau)
+            if objective(A, new) > objective(A, tau):
+                tau = new
+                S += 1
+                applied += 1
+                for x in (i, k):
+                    up[x] = best_positive(ade(A, tau, x))
+                for y in (j, t0):
+                    lo[y] = best_positive(jde(A, tau, y))
+        if applied == 0:
+            break
+    return tau, objective(A, tau), S, attempts, passes

@@ -312,3 +312,67 @@ def test_parallel_prefix_and_resume():
     assert list(rest["tau"]) == list(full["tau"]) and rest["f"] == full["f"]
     g, _ = oracle.scan(A, full["tau"])
     assert g.max() <= 0
+
+
+# Lazy DGS (Algorithm 1 as printed), worked by hand from the identity start
+# (f = 13).  Pass 1: stored agent bests (6, job 2), (5, job 0), (6, job 0) and
+# job bests (6, agent 2), (5, agent 0), (6, agent 0) (job 1: agents 0 and 2
+# tie at 5, the lower agent is kept).  Attempt 1: the maxima tie at 6 and the
+# strict comparison takes the job branch: agent 2 takes job 0 (+6, f = 19);
+# agents 0, 2 and jobs 0, 2 are re-evaluated: (1, job 1), (3, job 1) and
+# (3, agent 1), (1, agent 1).  Attempt 2: stale maxima 5 and 5, job branch:
+# agent 0 takes job 1 (+1, f = 20); agents 0, 1 and jobs 1, 2 fall to 0.
+# Attempt 3: job 0's stale (3, agent 1) is now worth -2: not applied.
+# Attempt 4: agent 2's stale (3, job 1) is worth -2: not applied.  Pass 2
+# finds no improving exchange.  Steepest ascent reaches f = 22 instead.
+LAZY_A = [[5, 5, 9], [7, 2, 7], [8, 6, 6]]
+
+
+def test_lazy_worked_example():
+    ident = [0, 1, 2]
+    r = oracle.lazy_dgs(np.array(LAZY_A), init=ident)
+    assert list(r["tau"]) == [1, 2, 0] and r["f"] == 20
+    assert (r["S"], r["attempts"], r["passes"]) == (2, 4, 2)
+    assert dgs_ref.lazy_dgs(LAZY_A, init=ident) == ([1, 2, 0], 20, 2, 4, 2)
+    assert oracle.dgs_full(np.array(LAZY_A), init=ident)["f"] == 22
+    # the stored bests of the first pass, from the definitions
+    assert [dgs_ref.best_positive(dgs_ref.ade(LAZY_A, ident, i)) for i in range(3)] == [(6, 2), (5, 0), (6, 0)]
+    assert [dgs_ref.best_positive(dgs_ref.jde(LAZY_A, ident, j)) for j in range(3)] == [(6, 2), (5, 0), (6, 0)]
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_lazy_matches_definitions_small(seed):
+    """The numpy oracle against the definitional statement (every gain by
+    re-summing f), plus what any run must satisfy: a permutation, every
+    switch an improvement (f >= start), a 2-swap local optimum at the end
+    (the last pass found nothing), f <= the brute-force optimum."""
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(1, 8))
+    A = rng.integers(-20, 20 if seed % 3 else 3, (n, n))
+    init = None if seed % 2 else list(rng.permutation(n))
+    r = oracle.lazy_dgs(A, init=init)
+    d = dgs_ref.lazy_dgs(A.tolist(), init=init)
+    assert (list(r["tau"]), r["f"], r["S"], r["attempts"], r["passes"]) == (list(d[0]), d[1], d[2], d[3], d[4])
+    start = dgs_ref.greedy(A.tolist()) if init is None else init
+    assert r["f"] >= dgs_ref.objective(A.tolist(), start)
+    assert r["attempts"] >= r["S"] and (r["passes"] >= 1)
+    assert all(g is None or g <= 0 for g, _ in dgs_ref.scan(A.tolist(), list(r["tau"])))
+    assert r["f"] <= brute.optimum(A.tolist())[0]
+
+
+def test_lazy_two_agents_is_optimal():
+    for A in ([[1, 5], [5, 1]], [[5, 1], [1, 5]], [[3, 3], [3, 3]], [[0, 7], [2, 0]]):
+        r = oracle.lazy_dgs(np.array(A), init=[0, 1])
+        assert r["f"] == brute.optimum(A)[0]
+
+
+def test_lazy_anytime_prefix():
+    A = gen.lowrank_matrix(200, 4)
+    full = oracle.lazy_dgs(A)
+    fs = []
+    for k in range(0, 6):
+        p = oracle.lazy_dgs(A, max_switches=k)
+        assert p["S"] == min(k, full["S"])
+        fs.append(p["f"])
+    assert all(b > a for a, b in zip(fs, fs[1:]))
+    assert oracle.lazy_dgs(A, max_switches=full["S"])["f"] == full["f"]
