@@ -70,6 +70,19 @@ typedef enum dgs_status {
  * number of ROUNDS (< 0: no bound).  Ends at a 2-exchange local optimum like
  * the default mode, by another trajectory.  n <= 262144. */
 #define DGS_PARALLEL 0x8u
+/* dgs_solve_ex: lazy DGS, Algorithm 1 as printed.  Each pass evaluates every
+ * agent (best job, lowest job on ties) and every job (best agent to take it,
+ * lowest agent on ties) and stores the positive improvements; then, while a
+ * stored improvement is positive, it follows the agent's stored exchange if
+ * the largest stored agent value is strictly larger than the largest stored
+ * job value, else the job's (lowest index on ties), zeroes the value it
+ * followed, applies the exchange only if it raises f and then re-evaluates
+ * only the two agents and two jobs involved (the other stored values stay
+ * stale).  Passes repeat until one applies nothing.  Ends at a 2-exchange
+ * local optimum by the paper's own trajectory.  dgs_result.rounds = passes,
+ * dgs_result.attempts = exchanges tried.  n <= 16384; not combinable with
+ * DGS_PARALLEL. */
+#define DGS_LAZY 0x10u
 
 /* dgs_result.phase_ms indices (filled only with DGS_PROFILE) */
 #define DGS_PHASE_RANGE 0  /* value-range check of the benefit matrix */
@@ -102,7 +115,8 @@ typedef struct dgs_result {
     int64_t stalls;          /* switching rounds that applied no switch (waited for a re-evaluation) */
     float device_ms;         /* device time of the solve (HIP events) */
     float phase_ms[DGS_NUM_PHASES]; /* per-phase device time (DGS_PROFILE only, else 0) */
-    int64_t rounds;          /* DGS_PARALLEL: rounds that applied at least one exchange (else 0) */
+    int64_t rounds;          /* DGS_PARALLEL: rounds that applied at least one exchange; DGS_LAZY: passes (else 0) */
+    int64_t attempts;        /* DGS_LAZY: exchanges tried, applied or not (else 0) */
 } dgs_result;
 
 /* Solve one instance with default options (greedy start, run to the end).

@@ -27,6 +27,7 @@ DGS_DEVICE_PTRS = 0x1
 DGS_PROFILE = 0x2
 DGS_AUTOTUNE = 0x4
 DGS_PARALLEL = 0x8
+DGS_LAZY = 0x10
 PHASES = ("range", "init", "layout", "scan", "switch")
 MAX_ABS_BENEFIT = (1 << 29) - 1
 
@@ -62,12 +63,13 @@ class Result(ctypes.Structure):
                 ("stalls", ctypes.c_int64),
                 ("device_ms", ctypes.c_float),
                 ("phase_ms", ctypes.c_float * 5),
-                ("rounds", ctypes.c_int64)]
+                ("rounds", ctypes.c_int64),
+                ("attempts", ctypes.c_int64)]
 
     def as_dict(self):
         return dict(initial_benefit=int(self.initial_benefit), total_benefit=int(self.total_benefit),
                     switches=int(self.switches), rescans=int(self.rescans), stalls=int(self.stalls),
-                    rounds=int(self.rounds), device_ms=float(self.device_ms),
+                    rounds=int(self.rounds), attempts=int(self.attempts), device_ms=float(self.device_ms),
                     phase_ms={p: float(self.phase_ms[i]) for i, p in enumerate(PHASES)})
 
 
@@ -164,7 +166,8 @@ def _torch_stream_ptr():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def solve(A, init=None, max_switches: int = -1, profile: bool = False, parallel: bool = False):
+def solve(A, init=None, max_switches: int = -1, profile: bool = False, parallel: bool = False,
+          lazy: bool = False):
     """Run DGS on one instance.
 
     A: n x n int32 benefit matrix (numpy / CPU tensor, or a ROCm tensor).
@@ -175,10 +178,13 @@ def solve(A, init=None, max_switches: int = -1, profile: bool = False, parallel:
     parallel: Parallel DGS (Algorithm 3 with Check Conflicts, Algorithm 4):
     every round applies all non-conflicting improving exchanges at once;
     max_switches then bounds the rounds (result["rounds"]).
+    lazy: Algorithm 1 as printed (stale agent and job bests, the paper's
+    branch rule and improvement guard); result["rounds"] = passes,
+    result["attempts"] = exchanges tried.
     """
     L = lib()
     n = _square_n(A)
-    extra = (DGS_PROFILE if profile else 0) | (DGS_PARALLEL if parallel else 0)
+    extra = (DGS_PROFILE if profile else 0) | (DGS_PARALLEL if parallel else 0) | (DGS_LAZY if lazy else 0)
     opt = Options(max_switches=int(max_switches), init_assign=None, flags=extra, stream=None)
     res = Result()
     if _is_device_tensor(A):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgs.so")
-SOURCES = ["dgs_kernels.hip", "dgs_greedy.hip", "dgs_scan.hip", "dgs_switch3.hip", "dgs_batch.hip", "dgs_parallel.hip", "dgs_api.cpp", "dgs_plan.cpp",
+SOURCES = ["dgs_kernels.hip", "dgs_greedy.hip", "dgs_scan.hip", "dgs_switch3.hip", "dgs_batch.hip", "dgs_parallel.hip", "dgs_lazy.hip", "dgs_api.cpp", "dgs_plan.cpp",
            "dgs_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

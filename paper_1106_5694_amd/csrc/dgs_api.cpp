@@ -260,6 +260,7 @@ struct Call {
     bool profile;
     bool coop = true;  // cooperative switching launch (else the caller owns co-residency)
     bool parallel = false;  // Parallel DGS rounds instead of the switching loop (max_switches = max rounds)
+    bool lazy = false;      // lazy DGS passes (Algorithm 1 as printed) instead of the switching loop
     hipStream_t stream;
 };
 
@@ -285,11 +286,41 @@ dgs_status parallel_rounds(const Instance &I, Workspace *w, int64_t max_rounds, 
     return DGS_OK;
 }
 
+// Lazy DGS (Algorithm 1 as printed): passes of a full evaluation of agents
+// (into I.bk) and jobs (per owner agent, into I.bb, free in this mode)
+// followed by the single-workgroup switching phase, until a pass applies
+// nothing or max_switches is reached.  d must be current; the passes keep it.
+dgs_status lazy_passes(const Instance &I, Workspace *w, int64_t max_switches, int64_t *passes_out, hipStream_t s) {
+    int64_t passes = 0, S = 0;
+    int64_t *hs = w->host_stats + 10;  // [0..5] = stats[0..5]
+    while (max_switches < 0 || S < max_switches) {
+        DGS_HIP(launch_scan_best_transposed(I, I.scan, s, false, I.bk, nullptr));
+        DGS_HIP(launch_scan_best_transposed(I, I.scan, s, true, I.bb, nullptr));
+        ++passes;
+        DGS_HIP(launch_lazy_pass(I, I.bb, max_switches, s));
+        DGS_HIP(hipMemcpyAsync(hs, I.stats, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        DGS_HIP(hipStreamSynchronize(s));
+        S = hs[0];
+        if (hs[5] == 0) break;
+    }
+    *passes_out = passes;
+    return DGS_OK;
+}
+
 // The whole device pipeline of one instance.
 dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *gain_out, int32_t *job_out,
                         dgs_result *res) {
     const int32_t n = c.n;
     hipStream_t s = c.stream;
+    if (c.parallel && n > parallel_max_agents()) {
+        set_error("parallel mode supports n <= %d", parallel_max_agents());
+        return DGS_E_INVAL;
+    }
+    if (c.lazy && (c.parallel || n > kLazyMaxN)) {
+        set_error(c.parallel ? "DGS_LAZY and DGS_PARALLEL exclude each other" : "lazy mode supports n <= %d",
+                  kLazyMaxN);
+        return DGS_E_INVAL;
+    }
     if (c.assign_in) {
         dgs_status st = check_init(c.assign_in, n, c.dev, s);
         if (st != DGS_OK) return st;
@@ -302,10 +333,6 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         ~Guard() { release_ws(w); }
     } guard{w};
 
-    if (c.parallel && n > parallel_max_agents()) {
-        set_error("parallel mode supports n <= %d", parallel_max_agents());
-        return DGS_E_INVAL;
-    }
     const int grid = std::max(1, std::min(g_ctx.loop_grid, (int)n));
     if (vec_layout(n, grid).total > w->vec_bytes) {
         set_error("internal: workspace too small for n=%d", n);
@@ -333,19 +360,23 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     }
     DGS_HIP(mark(DGS_PHASE_LAYOUT));
     DGS_HIP(launch_transpose(A, I.AT, n, s));
-    if (c.parallel && mode == Mode::Solve)
+    const bool no_w = (c.parallel || c.lazy) && mode == Mode::Solve;  // these modes evaluate from AT
+    if (no_w)
         DGS_HIP(launch_benefits(A, I.tau, n, I.d, I.stats + 2, s));
     else
         DGS_HIP(launch_build_w(A, I.AT, I.tau, n, I.W, I.d, I.stats + 2, s));
     DGS_HIP(mark(DGS_PHASE_SCAN));
     if (c.parallel && mode == Mode::Solve)
         DGS_HIP(launch_scan_best_transposed(I, I.scan, s));
-    else
-        DGS_HIP(launch_scan_pairs(I, I.scan, s));
+    else if (!no_w)
+        DGS_HIP(launch_scan_pairs(I, I.scan, s));  // (lazy passes evaluate at their start)
     DGS_HIP(mark(DGS_PHASE_SWITCH));
     int64_t rounds = 0;
     if (mode == Mode::Solve && c.parallel) {
         st = parallel_rounds(I, w, c.max_switches, &rounds, s);
+        if (st != DGS_OK) return st;
+    } else if (mode == Mode::Solve && c.lazy) {
+        st = lazy_passes(I, w, c.max_switches, &rounds, s);
         if (st != DGS_OK) return st;
     } else if (mode == Mode::Solve) {
         // The loops exit at once when the range check failed.  n = 1 has no
@@ -400,6 +431,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         res->rescans = hs[3];
         res->stalls = hs[4];
         res->rounds = rounds;
+        res->attempts = c.lazy ? hs[7] : 0;
         res->device_ms = ms;
         for (int i = 0; i < DGS_NUM_PHASES; ++i) {
             float pm = 0.f;
@@ -713,6 +745,7 @@ dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out, 
     c.dev = opt && (opt->flags & DGS_DEVICE_PTRS);
     c.profile = opt && (opt->flags & DGS_PROFILE);
     c.parallel = opt && (opt->flags & DGS_PARALLEL);
+    c.lazy = opt && (opt->flags & DGS_LAZY);
     c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
     return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
 }

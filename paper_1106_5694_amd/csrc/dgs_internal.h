@@ -89,8 +89,11 @@ hipError_t launch_scan_rows(const Instance &I, hipStream_t s);
 size_t scan_pairs_scratch_bytes(int n);
 hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s);
 // The same evaluation read from A^T through tau (W need not be built), writing
-// only each agent's best (bk, bc): the per-round evaluation of Parallel DGS.
-hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s);
+// only each agent's best: into I.bk / I.bc (best == nullptr), else into best
+// (and partner, if not null).  by_agent keys each candidate by the partner
+// agent instead of its job (the best agent to take the agent's job).
+hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s, bool by_agent = false,
+                                       u64 *best = nullptr, int32_t *partner = nullptr);
 hipError_t launch_switch_loop(const Instance &I, int64_t max_switches, int grid, hipStream_t s);
 // Largest n of the switching loop with cooperative re-evaluation (16-bit agent and job fields).
 constexpr int kSwitchExMaxN = 65535;
@@ -131,6 +134,13 @@ int batch_grid_limit(int block);
 // advanced, stats[5] = accepted count) followed by the swaps.
 int parallel_max_agents();
 hipError_t launch_parallel_round(const Instance &I, int32_t *acc, hipStream_t s);
+
+// Lazy DGS (dgs_lazy.hip): the switching phase of one pass of Algorithm 1 as
+// printed, in one workgroup, for n <= kLazyMaxN.  Reads the pass's evaluation
+// (agent side in I.bk, job side per owner agent in jde); advances stats[0],
+// [1] and [7] (attempts) and sets stats[5] to the switches of the pass.
+constexpr int kLazyMaxN = 16384;
+hipError_t launch_lazy_pass(const Instance &I, const u64 *jde, int64_t max_switches, hipStream_t s);
 
 hipError_t launch_export_best(const Instance &I, int64_t *gain_out, int32_t *job_out,
                               hipStream_t s);

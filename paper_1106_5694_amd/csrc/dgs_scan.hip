@@ -57,7 +57,10 @@ struct ScanParams {
 // One workgroup of BLOCK threads per tile pair: BLOCK / 64 threads per tile
 // row, each scoring 64 / (BLOCK / 64) partners on each side; interior pairs
 // (no bounds, no diagonal) take an unrolled path.
-template <int BLOCK, bool kRows>
+// kByAgent: the candidate of agent i against partner k is keyed by k itself
+// instead of its job tau(k) -- the job side of the evaluation (the best agent
+// to take the job of agent i, lowest agent on ties).
+template <int BLOCK, bool kRows, bool kByAgent>
 __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     constexpr int Q = BLOCK / 64;  // threads per tile row
     constexpr int E = kTile / Q;   // partners per thread
@@ -103,11 +106,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     }
     if (t < kTile) {
         dI[t] = i0 + t < n ? P.d[i0 + t] : 0;
-        jI[t] = i0 + t < n ? P.tau[i0 + t] : 0;
+        jI[t] = i0 + t < n ? (kByAgent ? i0 + t : P.tau[i0 + t]) : 0;
     } else if (t < 2 * kTile) {
         const int x = t - kTile;
         dK[x] = k0 + x < n ? P.d[k0 + x] : 0;
-        jK[x] = k0 + x < n ? P.tau[k0 + x] : 0;
+        jK[x] = k0 + x < n ? (kByAgent ? k0 + x : P.tau[k0 + x]) : 0;
     }
     __syncthreads();
 
@@ -170,7 +173,7 @@ __global__ __launch_bounds__(256) void k_scan_best(const u64 *__restrict__ part,
     for (int s = 32; s >= 1; s >>= 1) m = umax64(m, shfl_xor64(m, s));
     if (lane == 0) {
         bk[r] = m;
-        bc[r] = m ? sigma[key_index(m)] : -1;
+        if (bc) bc[r] = m ? sigma[key_index(m)] : -1;
     }
 }
 
@@ -248,13 +251,18 @@ size_t scan_pairs_scratch_bytes(int n) {
     return (size_t)n * nb * 2 * sizeof(u64);
 }
 
-hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s) {
+hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s, bool by_agent, u64 *best,
+                                       int32_t *partner) {
     const int nb = (I.n + kTile - 1) / kTile;
     const long long pairs = (long long)nb * (nb + 1) / 2;
     ScanParams P{I.AT, I.tau, I.tau, I.d, (u64 *)scratch, I.n, nb};
-    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    if (by_agent)
+        hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true, true>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    else
+        hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s,
+                           P);
     hipLaunchKernelGGL(k_scan_best, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
-                       nb, I.sigma, I.bk, I.bc);
+                       nb, I.sigma, best ? best : I.bk, best ? partner : I.bc);
     return hipGetLastError();
 }
 
@@ -262,7 +270,7 @@ hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s) {
     const int nb = (I.n + kTile - 1) / kTile;
     const long long pairs = (long long)nb * (nb + 1) / 2;
     ScanParams P{I.W, nullptr, I.tau, I.d, (u64 *)scratch, I.n, nb};
-    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, false, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
                        nb, I.sigma, I.bk, I.bb, I.bc, I.lists);
     return hipGetLastError();

@@ -16,6 +16,10 @@ per thread.
 With ``--parallel`` it writes tests/golden/lowrank16384_parallel.txt: the
 oracle's Parallel DGS (Algorithm 3 with Check Conflicts) from the greedy
 start of the n = 16384 workload, seeds 1 and 2.
+
+With ``--lazy`` it writes tests/golden/lowrank16384_lazy.txt: the oracle's
+lazy DGS (Algorithm 1 as printed) from the greedy start of the n = 16384
+workload, seed 1.
 """
 from __future__ import annotations
 
@@ -36,6 +40,7 @@ OUT = os.path.join(HERE, "lowrank16384.txt")
 OUT_PREFIX = os.path.join(HERE, "lowrank20480_prefix.txt")
 PREFIX_N, PREFIX_K = 20480, 1000
 OUT_PARALLEL = os.path.join(HERE, "lowrank16384_parallel.txt")
+OUT_LAZY = os.path.join(HERE, "lowrank16384_lazy.txt")
 
 
 def main(seeds):
@@ -94,10 +99,32 @@ def parallel(seeds=(1, 2)):
         f.write("\n".join(lines) + "\n")
 
 
+def lazy(seeds=(1,)):
+    lines = ["# Oracle lazy DGS (Algorithm 1 as printed: stale agent and job bests, strict",
+             "# branch rule, improvement guard, passes until one applies nothing) on the",
+             "# n = 16384 low-rank-plus-noise workload (workloads.gen.lowrank_matrix(16384, seed)),",
+             "# greedy start; written by make_golden.py --lazy.  tau_sha256 as in lowrank16384.txt."]
+    for seed in seeds:
+        t0 = time.time()
+        A = gen.lowrank_matrix(16384, seed)
+        g = oracle.greedy(A)
+        r = oracle.lazy_dgs(A, init=g)
+        h = hashlib.sha256(np.ascontiguousarray(r["tau"], dtype="<i4").tobytes()).hexdigest()
+        lines += ["", f"[seed{seed}]", f"greedy_f = {oracle.objective(A, g)}", f"f = {r['f']}",
+                  f"S = {r['S']}", f"attempts = {r['attempts']}", f"passes = {r['passes']}", f"tau_sha256 = {h}"]
+        print(f"lazy seed {seed}: S={r['S']} attempts={r['attempts']} passes={r['passes']} f={r['f']} "
+              f"({time.time() - t0:.0f} s)", flush=True)
+        del A
+    with open(OUT_LAZY, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1:2] == ["--prefix"]:
         prefix()
     elif sys.argv[1:2] == ["--parallel"]:
         parallel()
+    elif sys.argv[1:2] == ["--lazy"]:
+        lazy()
     else:
         main([int(s) for s in sys.argv[1:]] or [1, 2, 3, 4, 5])
