@@ -144,6 +144,10 @@ def base_line(args, value: float, unit: str, ms_per_step: float, config: dict) -
     }
 
 
+def spec_n(workload: str) -> int:
+    return SINGLE[workload]["n"]
+
+
 def run_single(args, dgs, torch, gen, np) -> dict:
     spec = SINGLE[args.workload]
     n = spec["n"]
@@ -215,6 +219,30 @@ def run_parallel(args, dgs, torch, gen, np, steps: int = 3) -> dict:
     out = {"ms_per_solve": round(1000.0 * wall / steps, 3), "instances_per_s": round(steps / wall, 3),
            "rounds": r["rounds"], "switches": r["switches"], "initial_benefit": r["initial_benefit"],
            "total_benefit": r["total_benefit"],
+           "phase_ms": {p: round(float(np.mean([x["phase_ms"][p] for x in results])), 4) for p in dgs.PHASES}}
+    del Ad
+    return out
+
+
+def run_lazy(args, dgs, torch, gen, np, steps: int = 2) -> dict:
+    """Lazy DGS (Algorithm 1 as printed: stale agent and job bests, the
+    paper's branch rule and improvement guard) on the same instance; its own
+    trajectory, objective and switch count, reported beside the headline."""
+    A = gen.single_instance(args.workload, args.seed)
+    Ad = torch.from_numpy(A).to(torch.device("cuda:0"))
+    _, res = dgs.solve(Ad, profile=True, lazy=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        _, res = dgs.solve(Ad, profile=True, lazy=True)
+        results.append(res)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r = results[-1]
+    out = {"ms_per_solve": round(1000.0 * wall / steps, 3), "instances_per_s": round(steps / wall, 3),
+           "passes": r["rounds"], "attempts": r["attempts"], "switches": r["switches"],
+           "initial_benefit": r["initial_benefit"], "total_benefit": r["total_benefit"],
            "phase_ms": {p: round(float(np.mean([x["phase_ms"][p] for x in results])), 4) for p in dgs.PHASES}}
     del Ad
     return out
@@ -374,6 +402,8 @@ def main() -> int:
                     help="single-instance workloads: skip the batched summary")
     ap.add_argument("--no-parallel", action="store_true",
                     help="single-instance workloads: skip the Parallel DGS summary")
+    ap.add_argument("--no-lazy", action="store_true",
+                    help="single-instance workloads: skip the lazy DGS summary")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches): the reference "
@@ -410,6 +440,10 @@ def main() -> int:
             log("parallel DGS summary")
             line["parallel"] = run_parallel(args, dgs, torch, gen, np)
             log(f"parallel DGS: {line['parallel']}")
+        if not args.no_lazy and spec_n(args.workload) <= 16384:
+            log("lazy DGS summary")
+            line["lazy"] = run_lazy(args, dgs, torch, gen, np)
+            log(f"lazy DGS: {line['lazy']}")
         if not args.no_batched:
             log("batched workload summary")
             line["batched"] = run_batched(args, dgs, torch, gen, np, steps=3, warmup=1)
