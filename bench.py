@@ -36,6 +36,8 @@ SINGLE = {
     "lowrank16384": dict(n=16384, generator="round((1000*u_i)*c_j)+noise, u,c~U(0.1,1), noise~U{0..99}"),
     "lowrank4096": dict(n=4096, generator="round((1000*u_i)*c_j)+noise, u,c~U(0.1,1), noise~U{0..99}"),
     "uniform256": dict(n=256, generator="iid uniform int32 in [0,1000)"),
+    "geom4096": dict(n=4096, generator="GEOM: rounded Euclidean distances of random points in [0,1000]^2"),
+    "geom16384": dict(n=16384, generator="GEOM: rounded Euclidean distances of random points in [0,1000]^2"),
 }
 WORKLOADS = sorted(SINGLE) + ["batched512", "serving"]
 

@@ -17,6 +17,10 @@ With ``--parallel`` it writes tests/golden/lowrank16384_parallel.txt: the
 oracle's Parallel DGS (Algorithm 3 with Check Conflicts) from the greedy
 start of the n = 16384 workload, seeds 1 and 2.
 
+With ``--geom`` it writes tests/golden/geom16384.txt: steepest-ascent DGS,
+Parallel DGS and lazy DGS from the greedy start of the paper's GEOM instance
+type at n = 16384 (workloads.gen.geom_matrix(16384, 1)).
+
 With ``--lazy`` it writes tests/golden/lowrank16384_lazy.txt: the oracle's
 lazy DGS (Algorithm 1 as printed) from the greedy start of the n = 16384
 workload, seed 1.
@@ -41,6 +45,7 @@ OUT_PREFIX = os.path.join(HERE, "lowrank20480_prefix.txt")
 PREFIX_N, PREFIX_K = 20480, 1000
 OUT_PARALLEL = os.path.join(HERE, "lowrank16384_parallel.txt")
 OUT_LAZY = os.path.join(HERE, "lowrank16384_lazy.txt")
+OUT_GEOM = os.path.join(HERE, "geom16384.txt")
 
 
 def main(seeds):
@@ -119,6 +124,31 @@ def lazy(seeds=(1,)):
         f.write("\n".join(lines) + "\n")
 
 
+def geom(seed=1):
+    lines = ["# Oracle results on the paper's GEOM instance type (Section 4) at n = 16384:",
+             "# workloads.gen.geom_matrix(16384, seed), greedy start, run to the end, by",
+             "# steepest-ascent DGS (oracle dgs_incr), Parallel DGS and lazy DGS; written by",
+             "# make_golden.py --geom.  tau_sha256 as in lowrank16384.txt."]
+    t0 = time.time()
+    A = gen.geom_matrix(16384, seed)
+    g = oracle.greedy(A)
+    f0 = oracle.objective(A, g)
+    for name, fn in (("steepest", lambda: oracle.dgs_incr(A, init=g)),
+                     ("parallel", lambda: oracle.parallel_dgs(A, init=g)),
+                     ("lazy", lambda: oracle.lazy_dgs(A, init=g))):
+        r = fn()
+        h = hashlib.sha256(np.ascontiguousarray(r["tau"], dtype="<i4").tobytes()).hexdigest()
+        lines += ["", f"[{name}_seed{seed}]", f"greedy_f = {f0}", f"f = {r['f']}", f"S = {r['S']}"]
+        if "rounds" in r:
+            lines.append(f"rounds = {r['rounds']}")
+        if "attempts" in r:
+            lines += [f"attempts = {r['attempts']}", f"passes = {r['passes']}"]
+        lines.append(f"tau_sha256 = {h}")
+        print(f"geom {name}: S={r['S']} f={r['f']} ({time.time() - t0:.0f} s)", flush=True)
+    with open(OUT_GEOM, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1:2] == ["--prefix"]:
         prefix()
@@ -126,5 +156,7 @@ if __name__ == "__main__":
         parallel()
     elif sys.argv[1:2] == ["--lazy"]:
         lazy()
+    elif sys.argv[1:2] == ["--geom"]:
+        geom()
     else:
         main([int(s) for s in sys.argv[1:]] or [1, 2, 3, 4, 5])

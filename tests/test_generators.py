@@ -51,3 +51,17 @@ def test_sizes_and_permutation():
     assert sorted(p.tolist()) == list(range(1000))
     t = gen.poisson_arrivals(200.0, 5.0, 1)
     assert (np.diff(t) > 0).all() and 800 < len(t) < 1200
+
+
+def test_geom_matrix_is_a_rounded_distance_matrix():
+    # Section 4's GEOM type: a_ij = Euclidean distance of random points i and j
+    # in [0, 1000]^2, rounded to an integer
+    A = gen.geom_matrix(400, 2)
+    assert A.dtype == np.int32 and (A == A.T).all() and (np.diag(A) == 0).all()
+    assert A.min() >= 0 and A.max() <= int(np.ceil(1000 * np.sqrt(2)))
+    # rounding keeps the triangle inequality within 1.5 (three roundings of 0.5)
+    i, j, k = np.random.default_rng(0).integers(0, 400, (3, 2000))
+    assert (A[i, k] <= A[i, j] + A[j, k] + 1.5).all()
+    assert (A == gen.geom_matrix(400, 2)).all() and not (A == gen.geom_matrix(400, 3)).all()
+    # point i depends on (seed, i) only, so a smaller instance is a leading block
+    assert (gen.single_instance("geom4096", 1)[:50, :50] == gen.geom_matrix(50, 1)).all()

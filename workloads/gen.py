@@ -194,6 +194,10 @@ def single_instance(name: str, seed: int) -> np.ndarray:
         return lowrank_matrix(4096, seed)
     if name == "lowrank16384":
         return lowrank_matrix(16384, seed)
+    if name == "geom4096":
+        return geom_matrix(4096, seed)
+    if name == "geom16384":
+        return geom_matrix(16384, seed)
     raise KeyError(name)
 
 
