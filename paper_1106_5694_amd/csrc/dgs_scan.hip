@@ -114,6 +114,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     }
     __syncthreads();
 
+    // the row-indirect variant feeds best-only reductions: a top-1 suffices
+    auto push = [](u64 &b1, u64 &b2, u64 k) {
+        if constexpr (kRows)
+            b1 = umax64(b1, k);
+        else
+            top2_push(b1, b2, k);
+    };
     const int rt = t / Q, q = t % Q;
     u64 a1 = 0, a2 = 0, c1 = 0, c2 = 0;  // row rt of I against K; row rt of K against I
     if (I != K && i0 + kTile <= n && k0 + kTile <= n) {
@@ -121,8 +128,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int c = q * E + e;
-            top2_push(a1, a2, mk_key((tA[rt][c] + tB[c][rt]) - (di + dK[c]), jK[c]));
-            top2_push(c1, c2, mk_key((tA[c][rt] + tB[rt][c]) - (dI[c] + dk), jI[c]));
+            push(a1, a2, mk_key((tA[rt][c] + tB[c][rt]) - (di + dK[c]), jK[c]));
+            push(c1, c2, mk_key((tA[c][rt] + tB[rt][c]) - (dI[c] + dk), jI[c]));
         }
     } else {
         if (i0 + rt < n) {
@@ -130,7 +137,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
             for (int e = 0; e < E; ++e) {
                 const int k = q * E + e;
                 if (k0 + k >= n || (I == K && k == rt)) continue;
-                top2_push(a1, a2, mk_key((tA[rt][k] + tB[k][rt]) - (di + dK[k]), jK[k]));
+                push(a1, a2, mk_key((tA[rt][k] + tB[k][rt]) - (di + dK[k]), jK[k]));
             }
         }
         if (I != K && k0 + rt < n) {
@@ -138,15 +145,20 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
             for (int e = 0; e < E; ++e) {
                 const int i = q * E + e;
                 if (i0 + i >= n) continue;
-                top2_push(c1, c2, mk_key((tA[i][rt] + tB[rt][i]) - (dI[i] + dk), jI[i]));
+                push(c1, c2, mk_key((tA[i][rt] + tB[rt][i]) - (dI[i] + dk), jI[i]));
             }
         }
     }
     // merge the Q threads of each row (adjacent lanes)
 #pragma unroll
     for (int m = 1; m < Q; m <<= 1) {
-        top2_merge(a1, a2, shfl_xor64(a1, m), shfl_xor64(a2, m));
-        top2_merge(c1, c2, shfl_xor64(c1, m), shfl_xor64(c2, m));
+        if constexpr (kRows) {
+            a1 = umax64(a1, shfl_xor64(a1, m));
+            c1 = umax64(c1, shfl_xor64(c1, m));
+        } else {
+            top2_merge(a1, a2, shfl_xor64(a1, m), shfl_xor64(a2, m));
+            top2_merge(c1, c2, shfl_xor64(c1, m), shfl_xor64(c2, m));
+        }
     }
     if (q == 0 && i0 + rt < n) {
         u64 *o = P.part + ((size_t)(i0 + rt) * P.nb + K) * 2;
