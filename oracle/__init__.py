@@ -15,6 +15,8 @@ Contents:
     wrapped below with ctypes.
   * ``parallel_dgs`` (below) -- Algorithm 3 with Check Conflicts
     (Algorithm 4), rounds of the C scan and an index-order claim walk.
+  * ``rect_dgs`` (below) -- steepest-ascent DGS for n agents and m >= n
+    jobs: swaps with other agents and moves to unassigned jobs, numpy.
   * ``lazy_dgs`` (below) -- Algorithm 1 as printed (stale bests of agents
     and jobs, the branch rule, the improvement guard, repeated passes),
     with numpy row evaluations.
@@ -248,6 +250,56 @@ def lazy_dgs(A, init=None, max_switches=-1):
             break
     tau = tau.astype(np.int32)
     return dict(tau=tau, f=objective(A, tau), S=S, attempts=attempts, passes=passes)
+
+
+def rect_greedy(A):
+    """n x m (m >= n): agents in index order take their best free job, lowest
+    job on ties."""
+    A = np.asarray(A, dtype=np.int64)
+    n, m = A.shape
+    free = np.ones(m, dtype=bool)
+    tau = np.empty(n, dtype=np.int64)
+    for i in range(n):
+        row = np.where(free, A[i], np.iinfo(np.int64).min)
+        tau[i] = int(np.argmax(row))
+        free[tau[i]] = False
+    return tau
+
+
+def rect_dgs(A, init=None, max_switches=-1):
+    """Steepest-ascent DGS on an n x m benefit matrix (m >= n, the paper's n
+    providers and m receivers): agent i may take any other job j; if j has an
+    owner k, k takes tau(i) (a 2-exchange, gain a[i][j] + a[k][tau(i)] -
+    a[i][tau(i)] - a[k][j]), else tau(i) becomes unassigned (gain a[i][j] -
+    a[i][tau(i)]).  Each agent's best is the lowest job among its largest
+    gains; the best agent (lowest index on ties) is applied while its gain is
+    > 0, then every agent is evaluated afresh.  Returns dict(tau, f, S)."""
+    A = np.asarray(A, dtype=np.int64)
+    n, m = A.shape
+    tau = rect_greedy(A) if init is None else np.array(init, dtype=np.int64, copy=True)
+    S = 0
+    rows = np.arange(n)
+    while max_switches < 0 or S < max_switches:
+        owner = np.full(m, -1, dtype=np.int64)
+        owner[tau] = rows
+        d = A[rows, tau]
+        k = owner[None, :].repeat(n, 0)                       # owner of job j
+        has = k >= 0
+        kk = np.where(has, k, 0)
+        back = np.where(has, A[kk, tau[:, None]] - A[kk, np.arange(m)[None, :]], 0)
+        G = A - d[:, None] + back
+        G[rows, tau] = np.iinfo(np.int64).min
+        j = np.argmax(G, axis=1)
+        g = G[rows, j]
+        i = int(np.argmax(g))
+        if g[i] <= 0:
+            break
+        jj = int(j[i])
+        if owner[jj] >= 0:
+            tau[owner[jj]] = tau[i]
+        tau[i] = jj
+        S += 1
+    return dict(tau=tau.astype(np.int32), f=int(A[rows, tau].sum()), S=S)
 
 
 def hungarian(A):

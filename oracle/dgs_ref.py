@@ -20,6 +20,8 @@ exactly) on many small random instances.
     job, lowest index on ties
   * JDE (Section 3.3, job side of Algorithm 2): scan agents i' != sigma(j)
     in index order, keep the first strictly better one
+  * rectangular DGS (n agents, m >= n jobs): steepest ascent over swaps
+    with other agents and moves to unassigned jobs
   * lazy DGS (Algorithm 1 as printed): stale per-agent and per-job bests,
     the paper's branch rule and improvement guard, re-evaluation of the two
     agents and two jobs of an applied switch only, full passes repeated
@@ -200,3 +202,60 @@ def lazy_dgs(A, init=None, max_switches=-1):
         if applied == 0:
             break
     return tau, objective(A, tau), S, attempts, passes
+
+
+def rect_objective(A, tau):
+    return sum(A[i][tau[i]] for i in range(len(tau)))
+
+
+def rect_greedy(A):
+    """Agents in index order take their best free job, lowest job on ties."""
+    m = len(A[0])
+    taken = [False] * m
+    tau = []
+    for row in A:
+        best, bj = None, -1
+        for j in range(m):
+            if not taken[j] and (best is None or row[j] > best):
+                best, bj = row[j], j
+        tau.append(bj)
+        taken[bj] = True
+    return tau
+
+
+def rect_switch(i, j, tau):
+    """Agent i takes job j; its owner, if any, takes tau(i); else the old job of
+    i becomes unassigned."""
+    new = list(tau)
+    if j in new:
+        new[new.index(j)] = tau[i]
+    new[i] = j
+    return new
+
+
+def rect_dgs(A, init=None, max_switches=-1):
+    """Steepest ascent on the rectangular neighbourhood: every agent's best
+    change (first strictly better job in index order, gains by re-summing f),
+    the best agent (lowest index on ties) applied while its gain is > 0.
+    Returns (tau, f, S)."""
+    m = len(A[0])
+    tau = list(rect_greedy(A) if init is None else init)
+    S = 0
+    while max_switches < 0 or S < max_switches:
+        f0 = rect_objective(A, tau)
+        bi, bj, bg = -1, -1, 0
+        for i in range(len(tau)):
+            best, jb = None, -1
+            for j in range(m):
+                if j == tau[i]:
+                    continue
+                g = rect_objective(A, rect_switch(i, j, tau)) - f0
+                if best is None or g > best:
+                    best, jb = g, j
+            if best is not None and best > bg:
+                bi, bj, bg = i, jb, best
+        if bi < 0:
+            break
+        tau = rect_switch(bi, bj, tau)
+        S += 1
+    return tau, rect_objective(A, tau), S

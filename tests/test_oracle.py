@@ -376,3 +376,51 @@ def test_lazy_anytime_prefix():
         fs.append(p["f"])
     assert all(b > a for a, b in zip(fs, fs[1:]))
     assert oracle.lazy_dgs(A, max_switches=full["S"])["f"] == full["f"]
+
+
+# Rectangular DGS (n agents, m > n jobs), worked by hand: greedy gives
+# tau = [0, 2] (f = 7, job 1 free).  Both agents' best is their swap (+2);
+# agent 0 wins the tie: tau = [2, 0], f = 9.  Then agent 0's best is the move
+# to the free job 1 (+1): tau = [1, 0], f = 10, the optimum; nothing improves.
+RECT_A = [[3, 1, 0], [9, 0, 4]]
+
+
+def _rect_optimum(A):
+    n, m = len(A), len(A[0])
+    return max(sum(A[i][p[i]] for i in range(n)) for p in itertools.permutations(range(m), n))
+
+
+def test_rect_worked_example():
+    assert dgs_ref.rect_greedy(RECT_A) == [0, 2]
+    r = oracle.rect_dgs(np.array(RECT_A))
+    assert list(r["tau"]) == [1, 0] and r["f"] == 10 and r["S"] == 2
+    assert dgs_ref.rect_dgs(RECT_A) == ([1, 0], 10, 2)
+    assert oracle.rect_dgs(np.array(RECT_A), max_switches=1)["f"] == 9
+    assert _rect_optimum(RECT_A) == 10
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_rect_matches_definitions_small(seed):
+    """numpy oracle == definitional statement; no improving swap or move at
+    the end; f <= the brute-force optimum over injective assignments."""
+    rng = np.random.default_rng(7000 + seed)
+    n = int(rng.integers(1, 5))
+    m = int(rng.integers(n, n + 3))
+    A = rng.integers(-9, 10 if seed % 3 else 3, (n, m))
+    init = None if seed % 2 else [int(x) for x in rng.permutation(m)[:n]]
+    r = oracle.rect_dgs(A, init=init)
+    d = dgs_ref.rect_dgs(A.tolist(), init=init)
+    assert (list(r["tau"]), r["f"], r["S"]) == (list(d[0]), d[1], d[2])
+    L = A.tolist()
+    tau = list(r["tau"])
+    f = dgs_ref.rect_objective(L, tau)
+    assert all(dgs_ref.rect_objective(L, dgs_ref.rect_switch(i, j, tau)) <= f
+               for i in range(n) for j in range(m) if j != tau[i])
+    assert r["f"] <= _rect_optimum(L)
+
+
+def test_rect_square_is_steepest_ascent():
+    for seed in range(10):
+        A = gen.uniform_matrix(40, 0, 50 if seed % 2 else 4, 900 + seed)
+        r, s = oracle.rect_dgs(A), oracle.dgs_full(A)
+        assert list(r["tau"]) == list(s["tau"]) and r["f"] == s["f"] and r["S"] == s["S"]
