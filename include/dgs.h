@@ -129,6 +129,24 @@ dgs_status dgs_solve(const int32_t *benefit, int32_t n, int32_t *assign_out);
 dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out,
                         const dgs_options *opt, dgs_result *res);
 
+/* Rectangular instance: n agents, m >= n jobs (the paper's motivating n
+ * providers and m receivers, Section 1).  benefit is n*m int32, row-major;
+ * assign_out has n entries (distinct jobs in [0, m)); jobs nobody holds are
+ * unassigned.  Steepest-ascent DGS over two kinds of change: agent i takes
+ * job j from its owner k, who takes i's job (a 2-exchange), or agent i moves
+ * to an unassigned job j, leaving its old job unassigned (gain
+ * a[i][j] - a[i][tau(i)]).  Each agent's best is the lowest job among its
+ * largest gains; the best agent (lowest index on ties) is applied while its
+ * gain is > 0.  The greedy start lets agents 0..n-1 take their best free job
+ * in turn.  Implemented by padding to m x m with m - n agents of benefit 0
+ * (a move is the 2-exchange with the padding agent that holds the free job),
+ * so it takes m*m*4 bytes of device memory beyond the square path's needs.
+ * opt may be NULL; init_assign (n distinct jobs), max_switches,
+ * DGS_DEVICE_PTRS, DGS_PROFILE and stream apply; DGS_PARALLEL and DGS_LAZY
+ * are rejected (DGS_E_INVAL), as are m < n and a non-injective init_assign. */
+dgs_status dgs_solve_rect(const int32_t *benefit, int32_t n, int32_t m, int32_t *assign_out,
+                          const dgs_options *opt, dgs_result *res);
+
 /* Solve `count` independent instances of possibly different sizes in one
  * device pass (one persistent launch; small instances run one per
  * workgroup).  benefits[b] / assign_outs[b] / ns[b] describe instance b

@@ -33,7 +33,7 @@ MAX_ABS_BENEFIT = (1 << 29) - 1
 
 # Every symbol include/dgs.h declares.
 EXPORTS = (
-    "dgs_solve", "dgs_solve_ex", "dgs_solve_batched", "dgs_diff_eval",
+    "dgs_solve", "dgs_solve_ex", "dgs_solve_rect", "dgs_solve_batched", "dgs_diff_eval",
     "dgs_server_footprint", "dgs_server_create", "dgs_server_submit", "dgs_server_poll",
     "dgs_server_wait", "dgs_server_stats_get", "dgs_server_destroy",
     "dgs_status_string", "dgs_last_error", "dgs_version", "dgs_release_cached",
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
     i32 = ctypes.c_int32
     L.dgs_solve.argtypes = [P, i32, P]
     L.dgs_solve_ex.argtypes = [P, i32, P, ctypes.POINTER(Options), ctypes.POINTER(Result)]
+    L.dgs_solve_rect.argtypes = [P, i32, i32, P, ctypes.POINTER(Options), ctypes.POINTER(Result)]
     L.dgs_solve_batched.argtypes = [i32, P, P, P, P, ctypes.POINTER(Options)]
     L.dgs_diff_eval.argtypes = [P, i32, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(Result)]
     L.dgs_server_footprint.argtypes = [i32]
@@ -209,6 +210,46 @@ def solve(A, init=None, max_switches: int = -1, profile: bool = False, parallel:
         opt.init_assign = keep.ctypes.data
     st = L.dgs_solve_ex(Ah.ctypes.data, n, out.ctypes.data, ctypes.byref(opt), ctypes.byref(res))
     _check(st, "dgs_solve_ex")
+    return out, res.as_dict()
+
+
+def solve_rect(A, init=None, max_switches: int = -1, profile: bool = False):
+    """Steepest-ascent DGS on an n x m benefit matrix (n agents, m >= n jobs):
+    swaps between agents and moves to unassigned jobs (dgs_solve_rect).
+
+    A: n x m int32 (numpy / CPU tensor, or a ROCm tensor); init: optional n
+    distinct jobs.  Returns (tau, result) as solve() does.
+    """
+    L = lib()
+    shape = tuple(A.shape)
+    if len(shape) != 2 or shape[0] > shape[1]:
+        raise ValueError("benefit matrix must be n x m with n <= m")
+    n, m = int(shape[0]), int(shape[1])
+    opt = Options(max_switches=int(max_switches), init_assign=None, flags=DGS_PROFILE if profile else 0,
+                  stream=None)
+    res = Result()
+    if _is_device_tensor(A):
+        import torch
+        if A.dtype != torch.int32 or not A.is_contiguous():
+            raise ValueError("device benefit matrix must be contiguous int32")
+        out = torch.empty(n, dtype=torch.int32, device=A.device)
+        keep = None
+        if init is not None:
+            keep = init.to(device=A.device, dtype=torch.int32).contiguous()
+            opt.init_assign = keep.data_ptr()
+        opt.flags |= DGS_DEVICE_PTRS
+        opt.stream = _torch_stream_ptr()
+        st = L.dgs_solve_rect(A.data_ptr(), n, m, out.data_ptr(), ctypes.byref(opt), ctypes.byref(res))
+        _check(st, "dgs_solve_rect")
+        return out, res.as_dict()
+    Ah = np.ascontiguousarray(np.asarray(A), dtype=np.int32)
+    out = np.empty(n, dtype=np.int32)
+    keep = None
+    if init is not None:
+        keep = np.ascontiguousarray(np.asarray(init), dtype=np.int32).reshape(n)
+        opt.init_assign = keep.ctypes.data
+    st = L.dgs_solve_rect(Ah.ctypes.data, n, m, out.ctypes.data, ctypes.byref(opt), ctypes.byref(res))
+    _check(st, "dgs_solve_rect")
     return out, res.as_dict()
 
 

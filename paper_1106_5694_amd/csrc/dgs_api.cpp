@@ -754,6 +754,75 @@ dgs_status dgs_solve(const int32_t *benefit, int32_t n, int32_t *assign_out) {
     return dgs_solve_ex(benefit, n, assign_out, nullptr, nullptr);
 }
 
+dgs_status dgs_solve_rect(const int32_t *benefit, int32_t n, int32_t m, int32_t *assign_out,
+                          const dgs_options *opt, dgs_result *res) {
+    g_last_error.clear();
+    dgs_status st = check_common(benefit, m, assign_out);
+    if (st != DGS_OK) return st;
+    if (n < 1 || n > m) {
+        set_error("rectangular instance needs 1 <= n <= m (n=%d, m=%d)", n, m);
+        return DGS_E_INVAL;
+    }
+    if (opt && (opt->flags & (DGS_PARALLEL | DGS_LAZY))) {
+        set_error("rectangular instances use the steepest-ascent mode only");
+        return DGS_E_INVAL;
+    }
+    if ((st = ensure_context()) != DGS_OK) return st;
+    const bool dev = opt && (opt->flags & DGS_DEVICE_PTRS);
+    hipStream_t s = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
+    // padded start: the caller's n jobs, then the unused jobs in increasing order
+    std::vector<int32_t> init;
+    if (opt && opt->init_assign) {
+        init.resize((size_t)n);
+        if (dev) {
+            DGS_HIP(hipMemcpyAsync(init.data(), opt->init_assign, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+            DGS_HIP(hipStreamSynchronize(s));
+        } else {
+            std::copy(opt->init_assign, opt->init_assign + n, init.begin());
+        }
+        std::vector<char> used((size_t)m, 0);
+        for (int32_t i = 0; i < n; ++i) {
+            if (init[i] < 0 || init[i] >= m || used[(size_t)init[i]]) {
+                set_error("init_assign is not n distinct jobs of 0..m-1");
+                return DGS_E_INVAL;
+            }
+            used[(size_t)init[i]] = 1;
+        }
+        for (int32_t j = 0; j < m; ++j)
+            if (!used[(size_t)j]) init.push_back(j);
+    }
+    const size_t rows = (size_t)n * (size_t)m * 4, mat = (size_t)m * (size_t)m * 4;
+    int32_t *P = nullptr, *pinit = nullptr, *pout = nullptr;
+    struct Bufs {
+        int32_t **p[3];
+        ~Bufs() {
+            for (auto q : p)
+                if (*q) (void)hipFree(*q);
+        }
+    } bufs{{&P, &pinit, &pout}};
+    if (hipMalloc((void **)&P, mat) != hipSuccess || hipMalloc((void **)&pout, (size_t)m * 4) != hipSuccess ||
+        (!init.empty() && hipMalloc((void **)&pinit, (size_t)m * 4) != hipSuccess)) {
+        set_error("device allocation of the padded %d x %d instance failed", m, m);
+        return DGS_E_NOMEM;
+    }
+    DGS_HIP(hipMemcpyAsync(P, benefit, rows, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (m > n) DGS_HIP(hipMemsetAsync((char *)P + rows, 0, mat - rows, s));
+    if (pinit) DGS_HIP(hipMemcpyAsync(pinit, init.data(), (size_t)m * 4, hipMemcpyHostToDevice, s));
+    Call c;
+    c.benefit = P;
+    c.n = m;
+    c.assign_in = pinit;
+    c.max_switches = opt ? opt->max_switches : -1;
+    c.dev = true;
+    c.profile = opt && (opt->flags & DGS_PROFILE);
+    c.stream = s;
+    st = run_instance(c, Mode::Solve, pout, nullptr, nullptr, res);
+    if (st != DGS_OK) return st;
+    DGS_HIP(hipMemcpyAsync(assign_out, pout, (size_t)n * 4, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    DGS_HIP(hipStreamSynchronize(s));
+    return DGS_OK;
+}
+
 dgs_status dgs_diff_eval(const int32_t *benefit, int32_t n, const int32_t *assign, int64_t *gain_out,
                          int32_t *job_out, const dgs_options *opt, dgs_result *res) {
     g_last_error.clear();
