@@ -437,7 +437,7 @@ def main() -> int:
                          "kernel that scales the HBM byte counters of a profile")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the method runs each instance on a "
+        print("bench.py: measures one GPU only (every instance runs on a "
               "single device); --gpus must be 1", file=sys.stderr)
         return 2
 
