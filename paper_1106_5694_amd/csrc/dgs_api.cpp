@@ -298,10 +298,12 @@ dgs_status lazy_passes(const Instance &I, Workspace *w, int64_t max_switches, in
         DGS_HIP(launch_scan_best_transposed(I, I.scan, s, true, I.bb, nullptr));
         ++passes;
         DGS_HIP(launch_lazy_pass(I, I.bb, max_switches, s));
+        int32_t *err = (int32_t *)(w->host_stats + 9);  // rewritten by the final flags copy
         DGS_HIP(hipMemcpyAsync(hs, I.stats, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        DGS_HIP(hipMemcpyAsync(err, I.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         DGS_HIP(hipStreamSynchronize(s));
         S = hs[0];
-        if (hs[5] == 0) break;
+        if (hs[5] == 0 || *err != 0) break;  // a broken invariant is reported by the caller
     }
     *passes_out = passes;
     return DGS_OK;
