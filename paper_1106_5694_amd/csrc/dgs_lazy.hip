@@ -64,12 +64,22 @@ __device__ __forceinline__ u64 wave_max64(u64 v) {
 // Partners of one re-evaluation loaded together.
 constexpr int kEvalChunk = 8;
 static_assert(kLazyPer % kEvalChunk == 0, "chunks");
+// A row of A is staged in LDS in stretches of kStageInts entries (32 KiB,
+// the LDS left beside the stored values), so that the re-evaluation's reads
+// a[i][tau(e)] gather from LDS instead of sending one request per entry.
+constexpr int kStageInts = 8192;
+constexpr int kStagePer = kStageInts / kLazyThreads;
+static_assert(6 * kLazyWaves * 8 <= kStageInts * 4, "maxima fit in the stage");
 
 __global__ __launch_bounds__(kLazyThreads) void k_lazy_pass(LazyParams P) {
     __shared__ int32_t ga[kLazyMaxN];  // stored improvement of each agent (0: none)
     __shared__ int32_t gj[kLazyMaxN];  // stored improvement of each job (0: none)
-    __shared__ u64 wk[2][kLazyWaves];  // per-wave maxima of the stored agent / job keys
-    __shared__ u64 rk[4][kLazyWaves];  // per-wave maxima of the four re-evaluations
+    // a stretch of a row of A for the re-evaluation's gathered reads; the
+    // argmax's and the re-evaluation's per-wave maxima share its first bytes
+    // (never in use at the same time: barriers separate the phases)
+    __shared__ __align__(16) int32_t stage[kStageInts];
+    u64(*wk)[kLazyWaves] = (u64(*)[kLazyWaves])stage;        // [2][waves]: stored agent / job keys
+    u64(*rk)[kLazyWaves] = (u64(*)[kLazyWaves])stage + 2;    // [4][waves]: the four re-evaluations
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int n = P.n;
     const bool bad = P.flags[0] != 0;
@@ -154,37 +164,68 @@ __global__ __launch_bounds__(kLazyThreads) void k_lazy_pass(LazyParams P) {
         gains += gain;
         __syncthreads();  // the switch is visible to the workgroup
         u64 kai = 0, kac = 0, kjj = 0, kjt = 0;
+        // partners e = t + 1024 s, in two halves of kEvalChunk per thread
 #pragma nounroll
         for (int s0c = 0; s0c < kLazyPer; s0c += kEvalChunk) {
-            int te[kEvalChunk], de[kEvalChunk], wj[kEvalChunk], wt[kEvalChunk];
+            int te[kEvalChunk];  // jobs after the switch
 #pragma unroll
             for (int u = 0; u < kEvalChunk; ++u) {
                 const int x = t + (s0c + u) * kLazyThreads;
-                const int xx = x < n ? x : 0;  // clamped: every load issued, none out of bounds
-                te[u] = P.tau[xx];
-                de[u] = P.d[xx];
-                wj[u] = P.AT[(size_t)j * n + xx];
-                wt[u] = P.AT[(size_t)t0 * n + xx];
+                te[u] = P.tau[x < n ? x : 0];  // clamped: every load issued, none out of bounds
             }
+#pragma nounroll
+            for (int side = 0; side < 2; ++side) {
+                const int r = side == 0 ? i : c;  // row of A read through tau
+                int va[kEvalChunk];                // a[r][tau(e)], gathered from LDS stretch by stretch
 #pragma unroll
-            for (int u = 0; u < kEvalChunk; ++u) {
-                const int x = t + (s0c + u) * kLazyThreads;
-                const int vi = P.A[(size_t)i * n + te[u]];
-                const int vc = P.A[(size_t)c * n + te[u]];
-                if (x < n) {
-                    const int g1 = (vi + wj[u]) - (ai + de[u]);
-                    const int g2 = (vc + wt[u]) - (ac + de[u]);
-                    if (x != i) {
-                        kai = umax64(kai, mk_key(g1, te[u]));
-                        kjj = umax64(kjj, mk_key(g1, x));
+                for (int u = 0; u < kEvalChunk; ++u) va[u] = 0;
+#pragma nounroll
+                for (int h0 = 0; h0 < n; h0 += kStageInts) {
+                    const int len = min(kStageInts, n - h0);
+                    int v[kStagePer];
+#pragma unroll
+                    for (int u = 0; u < kStagePer; ++u) {
+                        const int q = t + u * kLazyThreads;
+                        v[u] = P.A[(size_t)r * n + h0 + (q < len ? q : 0)];
                     }
-                    if (x != c) {
-                        kac = umax64(kac, mk_key(g2, te[u]));
-                        kjt = umax64(kjt, mk_key(g2, x));
+                    __syncthreads();  // the previous stretch (or the maxima) is no longer read
+#pragma unroll
+                    for (int u = 0; u < kStagePer; ++u) {
+                        const int q = t + u * kLazyThreads;
+                        if (q < len) stage[q] = v[u];
                     }
+                    __syncthreads();
+#pragma unroll
+                    for (int u = 0; u < kEvalChunk; ++u) {
+                        const int q = te[u] - h0;
+                        if (q >= 0 && q < len) va[u] = stage[q];
+                    }
+                }
+                // agent r's candidates (keyed by job) and those of its new job
+                // (keyed by agent) share g(e) = a[r][tau(e)] + a[e][job] - d(r) - d(e)
+                const int jr = side == 0 ? j : t0;
+                const int dr = side == 0 ? ai : ac;
+                u64 ka = 0, kj = 0;
+#pragma unroll
+                for (int u = 0; u < kEvalChunk; ++u) {
+                    const int x = t + (s0c + u) * kLazyThreads;
+                    const int xx = x < n ? x : 0;
+                    const int g = (va[u] + P.AT[(size_t)jr * n + xx]) - (dr + P.d[xx]);
+                    if (x < n && x != r) {
+                        ka = umax64(ka, mk_key(g, te[u]));
+                        kj = umax64(kj, mk_key(g, x));
+                    }
+                }
+                if (side == 0) {
+                    kai = umax64(kai, ka);
+                    kjj = umax64(kjj, kj);
+                } else {
+                    kac = umax64(kac, ka);
+                    kjt = umax64(kjt, kj);
                 }
             }
         }
+        __syncthreads();  // the last stretch is no longer read: the maxima reuse its bytes
         kai = wave_max64(kai);
         kac = wave_max64(kac);
         kjj = wave_max64(kjj);
