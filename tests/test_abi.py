@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -72,3 +73,14 @@ def test_binding_flags_and_result_fields_match_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = re.findall(r"\b([a-z_]+)(?:\[[A-Z_]+\])?;", body)
     assert fields == [f for f, _ in dgs.Result._fields_]
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no CPU fallback: without the built library every call raises
+    import paper_1106_5694_amd as dgs
+    monkeypatch.setattr(dgs, "LIB_PATH", str(tmp_path / "libdgs.so"))
+    monkeypatch.setattr(dgs, "_lib", None, raising=False)
+    with pytest.raises(RuntimeError):
+        dgs.lib()
+    with pytest.raises(RuntimeError):
+        dgs.solve(np.zeros((4, 4), dtype=np.int32))
