@@ -98,3 +98,24 @@ def test_geom16384_golden(dgs, geom16384, mode):
     if mode == "lazy":
         assert res["attempts"] == int(gold["attempts"]) and res["rounds"] == int(gold["passes"])
     assert h == gold["tau_sha256"]
+
+
+def test_batched_and_plan_on_geom(dgs):
+    # the one-workgroup-per-instance solver on the paper's instance type:
+    # sizes across its whole range, the largest beyond it (solved alone)
+    ns = [2, 63, 64, 500, 1024, 2048, 2049, 3000]
+    As = [gen.geom_matrix(n, 80 + i) for i, n in enumerate(ns)]
+    say(f"geom batched: {ns}")
+    refs = [oracle.dgs_incr(A) for A in As]
+    taus, results = dgs.solve_batched(As)
+    for ref, tau, res in zip(refs, taus, results):
+        assert (tau == ref["tau"]).all() and res["total_benefit"] == ref["f"] and res["switches"] == ref["S"]
+    small = [(A, ref) for A, ref in zip(As, refs) if A.shape[0] <= 2048]
+    plan = dgs.BatchPlan([A.shape[0] for A, _ in small])
+    try:
+        for rep in range(3):  # replays of the captured graph, eager checks between them
+            taus, results = plan.run([A for A, _ in small])
+            for (A, ref), tau, res in zip(small, taus, results):
+                assert (tau == ref["tau"]).all() and res["total_benefit"] == ref["f"], rep
+    finally:
+        plan.close()
