@@ -68,7 +68,10 @@ typedef enum dgs_status {
  * agent claims both), and applies all accepted exchanges at once.  It stops
  * when no agent has a positive best exchange; max_switches then bounds the
  * number of ROUNDS (< 0: no bound).  Ends at a 2-exchange local optimum like
- * the default mode, by another trajectory.  n <= 262144. */
+ * the default mode, by another trajectory.  n <= 262144.  In this mode and
+ * in DGS_LAZY the switching phase of phase_ms holds every round's (pass's)
+ * evaluation, rescans and stalls stay 0, and device_ms also spans the
+ * host's read of each round's (pass's) count. */
 #define DGS_PARALLEL 0x8u
 /* dgs_solve_ex: lazy DGS, Algorithm 1 as printed.  Each pass evaluates every
  * agent (best job, lowest job on ties) and every job (best agent to take it,
