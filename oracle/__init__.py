@@ -14,7 +14,8 @@ Contents:
     optimum.  Built by ``oracle/build.py`` into ``liboracle.so`` and
     wrapped below with ctypes.
   * ``parallel_dgs`` (below) -- Algorithm 3 with Check Conflicts
-    (Algorithm 4), rounds of the C scan and an index-order claim walk.
+    (Algorithm 4): rounds of the C agent and job scans and an index-order
+    claim walk over agents, then jobs.
   * ``rect_dgs`` (below) -- steepest-ascent DGS for n agents and m >= n
     jobs: swaps with other agents and moves to unassigned jobs, numpy.
   * ``lazy_dgs`` (below) -- Algorithm 1 as printed (stale bests of agents
@@ -54,6 +55,8 @@ def lib():
         L.orc_greedy.argtypes = [i32p, ctypes.c_int32, i32p]
         L.orc_scan.restype = None
         L.orc_scan.argtypes = [i32p, ctypes.c_int32, i32p, i64p, i32p]
+        L.orc_scan_jobs.restype = None
+        L.orc_scan_jobs.argtypes = [i32p, ctypes.c_int32, i32p, i64p, i32p]
         L.orc_dgs_full.restype = ctypes.c_int64
         L.orc_dgs_full.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int64,
                                    ctypes.POINTER(ctypes.c_int64), i32p, i32p, i64p,
@@ -105,6 +108,18 @@ def scan(A, tau):
     return g, j
 
 
+def scan_jobs(A, tau):
+    """Per-job best exchange (gain int64, agent int32): the agent that would
+    gain most by taking the job, its owner taking the agent's job; lowest
+    agent on ties; NEG_INF/-1 when n == 1."""
+    A = _mat(A)
+    n = A.shape[0]
+    g = np.empty(n, dtype=np.int64)
+    i = np.empty(n, dtype=np.int32)
+    lib().orc_scan_jobs(A, n, np.ascontiguousarray(tau, dtype=np.int32), g, i)
+    return g, i
+
+
 def _run(fn, A, init, max_switches, trace_cap, incremental):
     A = _mat(A)
     n = A.shape[0]
@@ -138,35 +153,53 @@ def dgs_incr(A, init=None, max_switches=-1, trace_cap=0):
     return _run(lib().orc_dgs_incr, A, init, max_switches, trace_cap, True)
 
 
+def check_conflicts(tau, ga, ja, gj, ij):
+    """Check Conflicts (Algorithm 4) on one round's evaluations: agent
+    exchanges (agent i to job ja[i], gain ga[i]) then job exchanges (agent
+    ij[j] to job j, gain gj[j]), each in index order, positive ones only.
+    Both agents of an exchange (for job j: the new agent and the current
+    owner) must be unclaimed for it to be kept; a kept exchange claims both.
+    Returns (kept agent pairs [(i, partner)], kept job pairs [(new agent,
+    owner)])."""
+    n = len(tau)
+    sigma = np.empty(n, dtype=np.int64)
+    sigma[tau] = np.arange(n)
+    claimed = np.zeros(n, dtype=bool)
+    kept_a, kept_j = [], []
+    for i in np.flatnonzero(ga > 0):
+        p = int(sigma[ja[i]])
+        if not (claimed[i] or claimed[p]):
+            claimed[i] = claimed[p] = True
+            kept_a.append((int(i), p))
+    for j in np.flatnonzero(gj > 0):
+        i, o = int(ij[j]), int(sigma[j])
+        if not (claimed[i] or claimed[o]):
+            claimed[i] = claimed[o] = True
+            kept_j.append((i, o))
+    return kept_a, kept_j
+
+
 def parallel_dgs(A, init=None, max_rounds=-1):
-    """Algorithm 3 with Check Conflicts (Algorithm 4), ADE only: each round
-    evaluates every agent afresh (the C scan), walks the agents with a positive
-    best exchange in index order, accepts agent i unless i or i' = sigma(j_i)
-    (the current owner of i's best job) is claimed by an accepted agent before
-    it, and applies all accepted exchanges (they are disjoint, so each gain is
-    exact and f grows by their sum).  Stops when no agent has a positive best.
-    Returns dict(tau, f, S = switches applied, rounds)."""
+    """Parallel DGS (Algorithm 3 with Check Conflicts, Algorithm 4): each
+    round evaluates every agent (C scan) and every job (C job scan) afresh,
+    keeps the exchanges ``check_conflicts`` lets through and applies them all
+    (they share no agent, so each gain is exact and f grows by their sum).
+    Stops when a round keeps nothing (no exchange improves f).
+    Returns dict(tau, f, S = exchanges applied, rounds)."""
     A = _mat(A)
-    n = A.shape[0]
     tau = greedy(A) if init is None else np.array(init, dtype=np.int32, copy=True)
     S = rounds = 0
     while max_rounds < 0 or rounds < max_rounds:
-        g, j = scan(A, tau)
-        sigma = np.empty(n, dtype=np.int32)
-        sigma[tau] = np.arange(n, dtype=np.int32)
-        claimed = np.zeros(n, dtype=bool)
-        acc = []
-        for i in np.flatnonzero(g > 0):
-            ip = int(sigma[j[i]])
-            if claimed[i] or claimed[ip]:
-                continue
-            claimed[i] = claimed[ip] = True
-            acc.append((int(i), ip))
-        if not acc:
+        ga, ja = scan(A, tau)
+        gj, ij = scan_jobs(A, tau)
+        kept_a, kept_j = check_conflicts(tau, ga, ja, gj, ij)
+        if not kept_a and not kept_j:
             break
-        for i, ip in acc:
-            tau[i], tau[ip] = tau[ip], tau[i]
-        S += len(acc)
+        new = tau.copy()
+        for x, y in kept_a + kept_j:
+            new[x], new[y] = tau[y], tau[x]
+        tau = new
+        S += len(kept_a) + len(kept_j)
         rounds += 1
     return dict(tau=tau, f=objective(A, tau), S=S, rounds=rounds)
 

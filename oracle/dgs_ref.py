@@ -20,6 +20,10 @@ exactly) on many small random instances.
     job, lowest index on ties
   * JDE (Section 3.3, job side of Algorithm 2): scan agents i' != sigma(j)
     in index order, keep the first strictly better one
+  * Parallel DGS (Algorithm 3 with Check Conflicts, Algorithm 4): fresh
+    agent and job evaluations per round, index-order claims of the two
+    agents of every exchange (agents first, then jobs), all kept exchanges
+    applied at once
   * rectangular DGS (n agents, m >= n jobs): steepest ascent over swaps
     with other agents and moves to unassigned jobs
   * lazy DGS (Algorithm 1 as printed): stale per-agent and per-job bests,
@@ -107,40 +111,69 @@ def dgs(A, init=None, max_switches=-1):
     return tau, objective(A, tau), S, trace
 
 
-def check_conflicts(rb, tau):
-    """Algorithm 4 (Check Conflicts), ADE part, read in index order: agent i with a
-    positive best (g_i, j_i) claims itself and i' = sigma(j_i), the current owner of
-    j_i, unless one of the two is claimed already (then i is in the conflict set).
-    Returns (accepted agents, conflict set)."""
+def check_conflicts(rb, jb, tau):
+    """Check Conflicts (Algorithm 4) over one round's fresh evaluations.
+
+    rb[i] = (gain, job) of agent i's best exchange (ADE), jb[j] = (gain,
+    agent) of job j's best exchange (JDE).  A positive agent exchange moves
+    agent i to job j_i and the current owner sigma(j_i) to tau(i); a positive
+    job exchange gives job j to agent i_j and moves the current owner sigma(j)
+    to tau(i_j).  Either one involves exactly two agents.  Agents are looked
+    at first, in index order, then jobs, in index order; an exchange is kept
+    when neither of its two agents has been claimed by an exchange kept before
+    it, and a kept exchange claims both.  A conflict drops only the exchange
+    that has it.
+
+    Returns (kept agent exchanges [(i, partner)], kept job exchanges
+    [(j, new agent, owner)], conflicting agents, conflicting jobs)."""
     sigma = inverse(tau)
     claimed = set()
-    accepted, conflicts = [], []
+    kept_a, kept_j, conf_a, conf_j = [], [], [], []
     for i, (g, j) in enumerate(rb):
         if g is None or g <= 0:
             continue
-        ip = sigma[j]
-        if i in claimed or ip in claimed:
-            conflicts.append(i)
+        pair = (i, sigma[j])
+        if claimed.intersection(pair):
+            conf_a.append(i)
         else:
-            claimed.update((i, ip))
-            accepted.append(i)
-    return accepted, conflicts
+            claimed.update(pair)
+            kept_a.append(pair)
+    for j, (g, i) in enumerate(jb):
+        if g is None or g <= 0:
+            continue
+        pair = (i, sigma[j])
+        if claimed.intersection(pair):
+            conf_j.append(j)
+        else:
+            claimed.update(pair)
+            kept_j.append((j, i, sigma[j]))
+    return kept_a, kept_j, conf_a, conf_j
+
+
+def job_scan(A, tau):
+    return [jde(A, tau, j) for j in range(len(tau))]
 
 
 def parallel_dgs(A, init=None, max_rounds=-1):
-    """Algorithm 3 (parallel DGS): every round evaluates all agents afresh, keeps
-    the non-conflicting positive exchanges (Algorithm 4) and applies them all.
-    Returns (tau, f, switches, rounds)."""
+    """Parallel DGS (Algorithm 3): every round evaluates every agent and every
+    job afresh, keeps the exchanges Check Conflicts lets through and applies
+    them all at once (they share no agent, so each gain is exact and f grows
+    by their sum).  Rounds repeat until none is kept, which happens exactly
+    when no exchange improves f.  Returns (tau, f, switches, rounds)."""
     tau = list(greedy(A) if init is None else init)
     S = rounds = 0
     while max_rounds < 0 or rounds < max_rounds:
-        rb = scan(A, tau)
-        accepted, _ = check_conflicts(rb, tau)
-        if not accepted:
+        rb, jb = scan(A, tau), job_scan(A, tau)
+        kept_a, kept_j, _, _ = check_conflicts(rb, jb, tau)
+        if not kept_a and not kept_j:
             break
-        for i in accepted:  # disjoint pairs: the order does not matter
-            tau = switch(i, rb[i][1], tau)
-        S += len(accepted)
+        new = list(tau)
+        for i, p in kept_a:
+            new[i], new[p] = tau[p], tau[i]
+        for _, i, o in kept_j:
+            new[i], new[o] = tau[o], tau[i]
+        tau = new
+        S += len(kept_a) + len(kept_j)
         rounds += 1
     return tau, objective(A, tau), S, rounds
 

@@ -17,6 +17,8 @@
  *   ADE         Algorithm 2: agent i scans every job j' != tau(i) and keeps
  *               the first strictly better exchange (so the lowest j' wins a
  *               tie); j_i and delta_i of Section 3.3.
+ *   JDE         Section 3.2: the job side of Algorithm 2 -- job j scans every
+ *               agent i != sigma(j) and keeps the first strictly better one.
  *   Switching   Section 3.3 and Algorithm 1: take the best exchange over all
  *               agents, apply it while it improves f, re-evaluate.
  *   Initial     Section 3.1: a greedy start that takes the benefits into
@@ -26,8 +28,10 @@
  * same readings):
  *   R1  Steepest ascent: after every switch the per-agent bests equal a
  *       fresh ADE of every agent; the switch taken is the global best.
- *   R2  ADE only (for a full square assignment JDE enumerates the same
- *       2-exchanges).
+ *   R2  Steepest ascent scans agents only (for a full square assignment JDE
+ *       enumerates the same 2-exchanges); JDE is kept for the job side of
+ *       Parallel DGS, where its tie-break (lowest agent) picks exchanges
+ *       that ADE's (lowest job) does not.
  *   R3  Ties: within an agent the lowest job index; across agents the
  *       lowest agent index.
  *   R4  A switch is applied only if its gain is strictly positive.
@@ -122,6 +126,33 @@ void orc_scan(const int32_t *A, int32_t n, const int32_t *tau, int64_t *g_out, i
     invert(tau, n, sigma);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) ade(A, n, tau, sigma, i, &g_out[i], &j_out[i]);
+    free(sigma);
+}
+
+/* JDE for one job (Section 3.2, the job side of Algorithm 2): the best
+ * agent i != sigma(j) to take job j -- its current owner then takes tau(i),
+ * so the gain is exchange_gain(i, j) -- scanning agents in index order and
+ * keeping the first strictly better one (lowest agent on ties).  Recorded
+ * even when <= 0; (ORC_NEG_INF, -1) when n == 1. */
+static void jde(const int32_t *A, int64_t n, const int32_t *tau, const int32_t *sigma,
+                int64_t j, int64_t *g_out, int32_t *i_out) {
+    int64_t bg = ORC_NEG_INF;
+    int32_t bi = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (i == sigma[j]) continue;
+        int64_t g = exchange_gain(A, n, tau, sigma, i, j);
+        if (g > bg) { bg = g; bi = (int32_t)i; }
+    }
+    *g_out = bg;
+    *i_out = bi;
+}
+
+/* Job difference evaluation of every job for the assignment tau. */
+void orc_scan_jobs(const int32_t *A, int32_t n, const int32_t *tau, int64_t *g_out, int32_t *i_out) {
+    int32_t *sigma = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    invert(tau, n, sigma);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t j = 0; j < n; ++j) jde(A, n, tau, sigma, j, &g_out[j], &i_out[j]);
     free(sigma);
 }
 

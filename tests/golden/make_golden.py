@@ -19,7 +19,15 @@ start of the n = 16384 workload, seeds 1 and 2.
 
 With ``--geom`` it writes tests/golden/geom16384.txt: steepest-ascent DGS,
 Parallel DGS and lazy DGS from the greedy start of the paper's GEOM instance
-type at n = 16384 (workloads.gen.geom_matrix(16384, 1)).
+type at n = 16384 (workloads.gen.geom_matrix(16384, 1)).  ``--geom parallel``
+(or any subset of steepest / parallel / lazy) rewrites only those sections.
+
+With ``--full20480`` it writes tests/golden/lowrank20480.txt: the oracle's
+complete runs (greedy start, to the end) of the n = 20480 instance (seed 1)
+by steepest-ascent DGS -- the size whose switching launch gathers more than
+8 exchange words per thread -- and by Parallel DGS, whose Check Conflicts
+takes its walking variant above n = 16384.  ``--full20480 parallel`` (or
+steepest) rewrites only that section.
 
 With ``--lazy`` it writes tests/golden/lowrank16384_lazy.txt: the oracle's
 lazy DGS (Algorithm 1 as printed) from the greedy start of the n = 16384
@@ -46,6 +54,34 @@ PREFIX_N, PREFIX_K = 20480, 1000
 OUT_PARALLEL = os.path.join(HERE, "lowrank16384_parallel.txt")
 OUT_LAZY = os.path.join(HERE, "lowrank16384_lazy.txt")
 OUT_GEOM = os.path.join(HERE, "geom16384.txt")
+OUT_FULL20480 = os.path.join(HERE, "lowrank20480.txt")
+
+
+def replace_sections(path, header, sections):
+    """Write `sections` ({name: [lines]}) into the golden file at `path`,
+    keeping every other section as it is (and `header` if the file is new)."""
+    old, order, cur = {}, [], None
+    head = list(header)
+    if os.path.exists(path):
+        head = []
+        for line in open(path).read().splitlines():
+            if line.startswith("[") and line.endswith("]"):
+                cur = line[1:-1]
+                order.append(cur)
+                old[cur] = []
+            elif cur is None:
+                head.append(line)
+            elif line:
+                old[cur].append(line)
+    for name, body in sections.items():
+        if name not in old:
+            order.append(name)
+        old[name] = body
+    out = [h for h in head if h]
+    for name in order:
+        out += ["", f"[{name}]"] + old[name]
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
 
 
 def main(seeds):
@@ -124,29 +160,53 @@ def lazy(seeds=(1,)):
         f.write("\n".join(lines) + "\n")
 
 
-def geom(seed=1):
-    lines = ["# Oracle results on the paper's GEOM instance type (Section 4) at n = 16384:",
-             "# workloads.gen.geom_matrix(16384, seed), greedy start, run to the end, by",
-             "# steepest-ascent DGS (oracle dgs_incr), Parallel DGS and lazy DGS; written by",
-             "# make_golden.py --geom.  tau_sha256 as in lowrank16384.txt."]
+def geom(seed=1, modes=("steepest", "parallel", "lazy")):
+    header = ["# Oracle results on the paper's GEOM instance type (Section 4) at n = 16384:",
+              "# workloads.gen.geom_matrix(16384, seed), greedy start, run to the end, by",
+              "# steepest-ascent DGS (oracle dgs_incr), Parallel DGS and lazy DGS; written by",
+              "# make_golden.py --geom.  tau_sha256 as in lowrank16384.txt."]
     t0 = time.time()
     A = gen.geom_matrix(16384, seed)
     g = oracle.greedy(A)
     f0 = oracle.objective(A, g)
-    for name, fn in (("steepest", lambda: oracle.dgs_incr(A, init=g)),
-                     ("parallel", lambda: oracle.parallel_dgs(A, init=g)),
-                     ("lazy", lambda: oracle.lazy_dgs(A, init=g))):
-        r = fn()
+    runs = {"steepest": lambda: oracle.dgs_incr(A, init=g),
+            "parallel": lambda: oracle.parallel_dgs(A, init=g),
+            "lazy": lambda: oracle.lazy_dgs(A, init=g)}
+    sections = {}
+    for name in modes:
+        r = runs[name]()
         h = hashlib.sha256(np.ascontiguousarray(r["tau"], dtype="<i4").tobytes()).hexdigest()
-        lines += ["", f"[{name}_seed{seed}]", f"greedy_f = {f0}", f"f = {r['f']}", f"S = {r['S']}"]
+        body = [f"greedy_f = {f0}", f"f = {r['f']}", f"S = {r['S']}"]
         if "rounds" in r:
-            lines.append(f"rounds = {r['rounds']}")
+            body.append(f"rounds = {r['rounds']}")
         if "attempts" in r:
-            lines += [f"attempts = {r['attempts']}", f"passes = {r['passes']}"]
-        lines.append(f"tau_sha256 = {h}")
+            body += [f"attempts = {r['attempts']}", f"passes = {r['passes']}"]
+        body.append(f"tau_sha256 = {h}")
+        sections[f"{name}_seed{seed}"] = body
         print(f"geom {name}: S={r['S']} f={r['f']} ({time.time() - t0:.0f} s)", flush=True)
-    with open(OUT_GEOM, "w") as f:
-        f.write("\n".join(lines) + "\n")
+    replace_sections(OUT_GEOM, header, sections)
+
+
+def full20480(seed=1, modes=("steepest", "parallel")):
+    header = [f"# Oracle results of complete runs (greedy start, to the end) on the n = {PREFIX_N}",
+              f"# low-rank-plus-noise workload (workloads.gen.lowrank_matrix({PREFIX_N}, seed)), written by",
+              "# make_golden.py --full20480: steepest-ascent DGS (the C oracle's incremental DGS) and",
+              "# Parallel DGS.  tau_sha256 as in lowrank16384.txt."]
+    t0 = time.time()
+    A = gen.lowrank_matrix(PREFIX_N, seed)
+    g = oracle.greedy(A)
+    runs = {"steepest": lambda: oracle.dgs_incr(A, init=g), "parallel": lambda: oracle.parallel_dgs(A, init=g)}
+    sections = {}
+    for name in modes:
+        r = runs[name]()
+        h = hashlib.sha256(np.ascontiguousarray(r["tau"], dtype="<i4").tobytes()).hexdigest()
+        body = [f"n = {PREFIX_N}", f"greedy_f = {oracle.objective(A, g)}", f"f = {r['f']}", f"S = {r['S']}"]
+        if "rounds" in r:
+            body.append(f"rounds = {r['rounds']}")
+        body.append(f"tau_sha256 = {h}")
+        sections[f"{name}_seed{seed}"] = body
+        print(f"n={PREFIX_N} {name} seed {seed}: S={r['S']} f={r['f']} ({time.time() - t0:.0f} s)", flush=True)
+    replace_sections(OUT_FULL20480, header, sections)
 
 
 if __name__ == "__main__":
@@ -157,6 +217,8 @@ if __name__ == "__main__":
     elif sys.argv[1:2] == ["--lazy"]:
         lazy()
     elif sys.argv[1:2] == ["--geom"]:
-        geom()
+        geom(modes=tuple(sys.argv[2:]) or ("steepest", "parallel", "lazy"))
+    elif sys.argv[1:2] == ["--full20480"]:
+        full20480(modes=tuple(sys.argv[2:]) or ("steepest", "parallel"))
     else:
         main([int(s) for s in sys.argv[1:]] or [1, 2, 3, 4, 5])

@@ -257,8 +257,63 @@ def test_parallel_worked_example():
     assert list(r["tau"]) == [1, 0, 2, 3] and r["f"] == 41 and r["S"] == 1 and r["rounds"] == 1
     assert dgs_ref.parallel_dgs(PAR_A, init=ident) == ([1, 0, 2, 3], 41, 1, 1)
     assert oracle.dgs_full(np.array(PAR_A), init=ident)["f"] == 50
-    acc, conf = dgs_ref.check_conflicts(dgs_ref.scan(PAR_A, ident), ident)
-    assert acc == [0] and conf == [1, 2]
+    ka, kj, ca, cj = dgs_ref.check_conflicts(dgs_ref.scan(PAR_A, ident), dgs_ref.job_scan(PAR_A, ident), ident)
+    assert ka == [(0, 1)] and kj == [] and ca == [1, 2] and cj == [0, 1, 2]
+
+
+# Worked by hand: Check Conflicts' job half keeps an exchange that the agent half
+# misses.  Start tau = [2, 3, 0, 1, 4], f = 1 + 7 + 18 + 4 + 20 = 50.
+# Agent bests (gain, job), lowest job on ties: agent 0 (25, job 1; partner 3),
+# agent 1 (11, job 2; partner 0), agent 2 (7, job 2; partner 0), agent 3 (25, job 2;
+# partner 0), agent 4 (6, job 1; partner 3 -- job 3 with partner 1 also gains 6).
+# Job bests (gain, agent), lowest agent on ties: job 0 (7, agent 0), job 1 (25, 0),
+# job 2 (25, 3), job 3 (11, 0), job 4 (6, agent 1 -- agent 3 also gains 6; owner 4).
+# Agent half: agent 0 is kept and claims {0, 3}; agents 1-4 each touch 0 or 3.
+# Job half: jobs 0-3 touch 0 or 3; job 4 (agent 1 takes it, owner 4 takes job 3:
+# 16 + 17 - 7 - 20 = 6) touches {1, 4}, unclaimed: kept.  Round 1 applies both,
+# f = 50 + 25 + 6 = 81 at tau = [1, 4, 0, 2, 3]; round 2 finds no improving exchange.
+CC5_A = [[8, 15, 1, 12, 3],
+         [9, 13, 7, 7, 16],
+         [18, 13, 18, 8, 0],
+         [0, 4, 15, 4, 11],
+         [2, 19, 7, 17, 20]]
+CC5_TAU = [2, 3, 0, 1, 4]
+
+
+def test_parallel_job_half_worked_example():
+    rb, jb = dgs_ref.scan(CC5_A, CC5_TAU), dgs_ref.job_scan(CC5_A, CC5_TAU)
+    assert rb == [(25, 1), (11, 2), (7, 2), (25, 2), (6, 1)]
+    assert jb == [(7, 0), (25, 0), (25, 3), (11, 0), (6, 1)]
+    ka, kj, ca, cj = dgs_ref.check_conflicts(rb, jb, CC5_TAU)
+    assert ka == [(0, 3)] and kj == [(4, 1, 4)] and ca == [1, 2, 3, 4] and cj == [0, 1, 2, 3]
+    assert dgs_ref.parallel_dgs(CC5_A, init=CC5_TAU) == ([1, 4, 0, 2, 3], 81, 2, 1)
+    r = oracle.parallel_dgs(np.array(CC5_A), init=CC5_TAU)
+    assert list(r["tau"]) == [1, 4, 0, 2, 3] and r["f"] == 81 and r["S"] == 2 and r["rounds"] == 1
+    g, i = oracle.scan_jobs(np.array(CC5_A), CC5_TAU)
+    assert list(g) == [7, 25, 25, 11, 6] and list(i) == [0, 0, 3, 0, 1]
+    # the end is a 2-swap local optimum
+    assert oracle.dgs_full(np.array(CC5_A), init=[1, 4, 0, 2, 3])["S"] == 0
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_job_scan_against_definition(seed):
+    """The C job scan equals JDE by re-summing f (every agent taking the job)."""
+    rng = np.random.default_rng(7000 + seed)
+    n = int(rng.integers(1, 9))
+    A = rng.integers(-6, 6 if seed % 2 else 3, (n, n))
+    tau = [int(x) for x in rng.permutation(n)]
+    g, i = oracle.scan_jobs(A, tau)
+    for j in range(n):
+        if n == 1:
+            assert g[0] == oracle.NEG_INF and i[0] == -1
+            continue
+        ref = dgs_ref.jde(A.tolist(), tau, j)
+        assert (int(g[j]), int(i[j])) == ref
+        # brute force over agents, lowest agent among the largest gains
+        gains = [(dgs_ref.objective(A.tolist(), dgs_ref.switch(a, j, tau)) - dgs_ref.objective(A.tolist(), tau), -a)
+                 for a in range(n) if tau[a] != j]
+        best = max(gains)
+        assert (int(g[j]), int(i[j])) == (best[0], -best[1])
 
 
 @pytest.mark.parametrize("name", ["2x2", "3x3 tie-break"])
@@ -271,36 +326,62 @@ def test_parallel_on_single_switch_examples(name):
 
 @pytest.mark.parametrize("seed", range(40))
 def test_parallel_properties_small(seed):
-    """Against the definitions: every round's accepted exchanges are disjoint and
-    positive, f grows by exactly their sum, the end is a 2-swap local optimum, the
-    C-scan version equals the definitional one, and f <= the brute-force optimum."""
+    """Against the definitions: every round's kept exchanges are disjoint and
+    positive, f grows by exactly their sum, no positive agent or job exchange
+    is left that touches no claimed agent (the claims are maximal over both
+    halves), the end is a 2-swap local optimum, the C-scan version equals the
+    definitional one, and f <= the brute-force optimum."""
     rng = np.random.default_rng(1000 + seed)
     n = int(rng.integers(2, 8))
     A = rng.integers(-20, 20 if seed % 2 else 3, (n, n))
-    tau = list(dgs_ref.greedy(A.tolist()))
+    tau = list(dgs_ref.greedy(A.tolist())) if seed % 3 else [int(x) for x in rng.permutation(n)]
+    start = list(tau)
     f = dgs_ref.objective(A.tolist(), tau)
     rounds = S = 0
     while True:
-        rb = dgs_ref.scan(A.tolist(), tau)
-        acc, conf = dgs_ref.check_conflicts(rb, tau)
-        if not acc:
-            assert all(g is None or g <= 0 for g, _ in rb)
+        rb, jb = dgs_ref.scan(A.tolist(), tau), dgs_ref.job_scan(A.tolist(), tau)
+        ka, kj, ca, cj = dgs_ref.check_conflicts(rb, jb, tau)
+        if not ka and not kj:
+            assert all(g is None or g <= 0 for g, _ in rb) and all(g is None or g <= 0 for g, _ in jb)
             break
         sigma = dgs_ref.inverse(tau)
-        pairs = [(i, sigma[rb[i][1]]) for i in acc]
+        pairs = list(ka) + [(i, o) for _, i, o in kj]
         used = [x for p in pairs for x in p]
         assert len(used) == len(set(used))  # disjoint
-        gain = sum(rb[i][0] for i in acc)
+        claimed = set(used)
+        for i, (g, j) in enumerate(rb):
+            if g is not None and g > 0:
+                assert {i, sigma[j]} & claimed  # maximal over the agent exchanges
+        for j, (g, i) in enumerate(jb):
+            if g is not None and g > 0:
+                assert {i, sigma[j]} & claimed  # and over the job exchanges
+        gain = sum(rb[i][0] for i, _ in ka) + sum(jb[j][0] for j, _, _ in kj)
         assert gain > 0
-        for i in acc:
+        for i, _ in ka:
             tau = dgs_ref.switch(i, rb[i][1], tau)
+        for j, i, _ in kj:
+            tau = dgs_ref.switch(i, j, tau)
         assert dgs_ref.objective(A.tolist(), tau) == f + gain
         f += gain
         rounds += 1
-        S += len(acc)
-    r = oracle.parallel_dgs(A)
+        S += len(pairs)
+    r = oracle.parallel_dgs(A, init=start)
     assert list(r["tau"]) == tau and r["f"] == f and r["S"] == S and r["rounds"] == rounds
     assert r["f"] <= brute.optimum(A)[0]
+
+
+def test_parallel_job_half_is_exercised():
+    """On small tie-heavy instances the job half keeps exchanges the agent half
+    cannot: the maximality check above is not vacuous for it."""
+    rng = np.random.default_rng(77)
+    hits = 0
+    for _ in range(400):
+        n = int(rng.integers(3, 8))
+        A = rng.integers(0, 4, (n, n)).tolist()
+        tau = [int(x) for x in rng.permutation(n)]
+        _, kj, _, _ = dgs_ref.check_conflicts(dgs_ref.scan(A, tau), dgs_ref.job_scan(A, tau), tau)
+        hits += bool(kj)
+    assert hits >= 5
 
 
 def test_parallel_prefix_and_resume():
