@@ -42,7 +42,7 @@ SINGLE = {
 WORKLOADS = sorted(SINGLE) + ["batched512", "serving"]
 
 KERNELS = {"range": "k_range_check", "init": "k_greedy_topk+k_greedy_resolve",
-           "layout": "k_transpose+k_build_w", "scan": "k_scan_pairs+k_scan_reduce",
+           "layout": "k_transpose+k_benefits", "scan": "k_scan_pairs+k_scan_reduce",
            "switch": "k_switch_v3"}
 KERNEL_SOURCES = {"k_switch_v3": "dgs_switch3.hip", "k_scan_pairs+k_scan_reduce": "dgs_scan.hip",
                   "k_batch_solve": "dgs_batch.hip"}
@@ -56,14 +56,21 @@ def algorithmic_bytes(phase: str, n: int, switches: int, rescans: int) -> int:
     if phase == "init":
         return 4 * nn  # greedy reads every entry once
     if phase == "layout":
-        return 16 * nn  # transpose (read + write) and working matrix (read + write)
+        return 8 * nn  # transpose (read + write)
     if phase == "scan":
         return 4 * nn  # every exchange pair (i, k) needs a_i,tau(k) and a_k,tau(i) once
     if phase == "switch":
         # per switch: the two changed candidates of every agent need 4 entries
-        # each (16n B); per full re-evaluation of one agent: two rows (8n B)
-        return 16 * n * switches + 8 * n * rescans
+        # each (16n B)
+        return 16 * n * switches
     raise KeyError(phase)
+
+
+def reevaluation_bytes(n: int, rescans: int) -> int:
+    """Bytes of the switching loop's own full re-evaluations of agents (two
+    rows each, 8n B): a cost of this design's exact rule, reported beside the
+    per-switch figure and not counted in it."""
+    return 8 * n * rescans
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -89,30 +96,59 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(A, switches: int, budget_s: float = 12.0) -> dict:
-    """Time the CPU oracle on a bounded sample of the same instance."""
-    import oracle
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+def _estimate(oracle, A, switches: int, budget_s: float, probe: int) -> tuple:
+    """Seconds per solve of the oracle at its current thread count: greedy +
+    first full evaluation timed, then a sample of switches sized to the
+    budget, extrapolated linearly to all switches.  Returns (est, sampled)."""
     t0 = time.perf_counter()
     tau0 = oracle.greedy(A)
     t_greedy = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.dgs_incr(A, init=tau0, max_switches=0)
     t_scan = time.perf_counter() - t0
-    # size the sample of switches from a short probe
-    k = min(switches, 200)
+    k = min(switches, probe)
     t0 = time.perf_counter()
     oracle.dgs_incr(A, init=tau0, max_switches=k)
-    t_probe = time.perf_counter() - t0 - t_scan
-    per = max(t_probe, 1e-9) / max(k, 1)
-    k2 = int(min(switches, max(k, (budget_s - t_greedy - t_scan) / per)))
+    per = max(time.perf_counter() - t0 - t_scan, 1e-9) / max(k, 1)
+    k2 = int(min(switches, max(k, (budget_s - t_greedy - 2 * t_scan) / per)))
     if k2 > k:
         t0 = time.perf_counter()
         oracle.dgs_incr(A, init=tau0, max_switches=k2)
         per = max(time.perf_counter() - t0 - t_scan, 1e-9) / k2
         k = k2
-    est = t_greedy + t_scan + per * switches
+    return t_greedy + t_scan + per * switches, k
+
+
+def cpu_baseline(A, switches: int, seed: int, budget_s: float = 12.0) -> dict:
+    """Time the CPU oracle on bounded samples: the headline instance on all
+    host threads (the reported baseline) and on one thread, and complete
+    solves of the n = 4096 instance of the same generator on both."""
+    import oracle
+    from workloads import gen
+
+    threads = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    est, k = _estimate(oracle, A, switches, budget_s, 200)
+    oracle.set_threads(1)
+    est1, k1 = _estimate(oracle, A, switches, budget_s / 2, 50)
+    A4 = gen.lowrank_matrix(4096, seed)
+    full4096 = {}
+    for th in (1, threads):
+        oracle.set_threads(th)
+        t0 = time.perf_counter()
+        r4 = oracle.dgs_incr(A4)
+        full4096[f"threads_{th}"] = round(time.perf_counter() - t0, 3)
+    oracle.set_threads(threads)
     return {
         "value": 1.0 / est,
         "unit": "instances/s",
@@ -121,6 +157,11 @@ def cpu_baseline(A, switches: int, budget_s: float = 12.0) -> dict:
         "sample": (f"greedy + first full evaluation + first {k} of {switches} switches of the same "
                    f"instance (C oracle, incremental re-evaluation, {threads} OpenMP threads), "
                    f"extrapolated linearly to all switches: est. {est:.2f} s per solve"),
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
+        "single_thread": {"est_s_per_solve": round(est1, 3), "switches_sampled": k1},
+        "lowrank4096_full_solve_s": full4096,
+        "lowrank4096_switches": int(r4["S"]),
     }
 
 
@@ -186,6 +227,13 @@ def run_single(args, dgs, torch, gen, np) -> dict:
                 "frac": d["hbm_frac"], "traffic": measured_traffic(kernel, args.workload),
                 "kernel": kernel, "phase": dominant, "algorithmic_bytes_per_launch": d["algorithmic_bytes"],
                 "avg_launch_ms": d["ms"]}
+    if dominant == "switch":
+        extra = reevaluation_bytes(n, rescans)
+        gbs = (d["algorithmic_bytes"] + extra) / (d["ms"] * 1e-3) / 1e9
+        roofline["bytes_basis"] = "16n B per switch (the two changed candidates of every agent)"
+        roofline["incl_reevaluation"] = {"bytes": d["algorithmic_bytes"] + extra, "GB/s": round(gbs, 1),
+                                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                         "basis": "plus 8n B per full re-evaluation of an agent"}
     config = {"workload": args.workload, "n": n, "seed": args.seed, "generator": spec["generator"],
               "start": "greedy", "switches": S, "rescans": rescans,
               "initial_benefit": results[-1]["initial_benefit"], "total_benefit": results[-1]["total_benefit"],
@@ -195,7 +243,7 @@ def run_single(args, dgs, torch, gen, np) -> dict:
     line["phases"] = phases
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(A, S)
+        line["cpu_baseline"] = cpu_baseline(A, S, args.seed)
     del Ad, tau
     torch.cuda.synchronize()
     return line
@@ -331,24 +379,19 @@ def run_batched(args, dgs, torch, gen, np, steps: int, warmup: int, count: int =
     }
 
 
-def run_serving(args, dgs, gen, np) -> dict:
-    """Poisson arrivals at 200/s for --serve-seconds, n log-uniform in
-    [128, 16384], low-rank-plus-noise benefits; the continuous-batching
-    server against a plain loop that solves one request at a time in
-    arrival order, on the same arrival trace."""
-    arrivals, pool_ns = gen.serving_trace(args.serve_seconds, 200.0, 128, 16384, args.seed, 64)
+def serving_pool(args, gen, size: int = 64):
+    """Distinct low-rank instances with sizes log-uniform in [128, 16384]
+    (pool instance p is seeded by (seed, p)); requests cycle through them."""
+    _, pool_ns = gen.serving_trace(1.0, 200.0, 128, 16384, args.seed, size)
     t0 = time.perf_counter()
     pool = [gen.lowrank_matrix(int(n), args.seed * 1_000_003 + p) for p, n in enumerate(pool_ns)]
-    log(f"generated the request pool ({len(pool)} instances) in {time.perf_counter() - t0:.1f} s; "
-        f"{len(arrivals)} requests over {args.serve_seconds} s")
-    reqs = [(float(t), k % len(pool)) for k, t in enumerate(arrivals)]
+    log(f"generated the request pool ({len(pool)} instances, {sum(A.nbytes for A in pool) / 1e9:.2f} GB) "
+        f"in {time.perf_counter() - t0:.1f} s")
+    return pool
 
-    # warm the library's workspaces for the larger sizes
-    for p in sorted(range(len(pool)), key=lambda p: -int(pool_ns[p]))[:2]:
-        dgs.solve(pool[p])
 
-    # continuous batching
-    log("serving: continuous batching")
+def _serve_continuous(dgs, pool, reqs) -> dict:
+    """The continuous-batching server (dgs_server_*) on an arrival trace."""
     with dgs.Server() as srv:
         start = time.perf_counter()
         tickets = []
@@ -359,19 +402,19 @@ def run_serving(args, dgs, gen, np) -> dict:
             tickets.append(srv.submit(pool[p]))
         for k, tk in enumerate(tickets):
             assert srv.wait(tk) is not None
-            if (k + 1) % 200 == 0:
+            if (k + 1) % 500 == 0:
                 log(f"serving: {k + 1} of {len(tickets)} requests done")
         st = srv.stats()
-    cb = {"requests": int(st["completed"]), "instances_per_s": round(st["inst_per_s"], 2),
-          "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1)}
-    log(f"serving: continuous batching done: {cb}")
+    return {"requests": int(st["completed"]), "completed_per_s": round(st["inst_per_s"], 2),
+            "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
+            "wall_s": round(time.perf_counter() - start, 2)}
 
-    # plain: one request at a time, in arrival order
-    log("serving: plain one-at-a-time loop")
-    lat = []
-    queue = []
+
+def _serve_plain(dgs, np, pool, reqs) -> dict:
+    """A plain loop that solves one request at a time (dgs_solve), in arrival
+    order, on the same arrival trace; latency = arrival to result."""
+    lat, queue, finished = [], [], []
     cv = threading.Condition()
-    finished = []
 
     def worker():
         while True:
@@ -385,7 +428,7 @@ def run_serving(args, dgs, gen, np) -> dict:
             dgs.solve(pool[p])
             finished.append(time.perf_counter())
             lat.append(finished[-1] - t_arr)
-            if len(lat) % 200 == 0:
+            if len(lat) % 500 == 0:
                 log(f"serving: plain loop, {len(lat)} requests done")
 
     th = threading.Thread(target=worker)
@@ -407,12 +450,41 @@ def run_serving(args, dgs, gen, np) -> dict:
         cv.notify()
     th.join()
     lat_us = np.asarray(lat) * 1e6
-    plain = {"requests": len(lat), "instances_per_s": round(len(lat) / max(finished[-1] - first_arrival, 1e-9), 2),
-             "p50_us": round(float(np.percentile(lat_us, 50)), 1),
-             "p99_us": round(float(np.percentile(lat_us, 99)), 1)}
-    log(f"serving: plain done: {plain}")
-    return {"arrival_rate_per_s": 200, "seconds": args.serve_seconds, "n_range": [128, 16384],
-            "pool": len(pool), "continuous_batching": cb, "plain_per_request": plain}
+    return {"requests": len(lat),
+            "completed_per_s": round(len(lat) / max(finished[-1] - first_arrival, 1e-9), 2),
+            "p50_us": round(float(np.percentile(lat_us, 50)), 1),
+            "p99_us": round(float(np.percentile(lat_us, 99)), 1),
+            "wall_s": round(time.perf_counter() - start, 2)}
+
+
+def run_serving(args, dgs, gen, np, pool, rate: float, seconds: float) -> dict:
+    """Poisson arrivals at `rate` per second for `seconds`, n log-uniform in
+    [128, 16384], low-rank-plus-noise benefits; the continuous-batching
+    server against the plain one-request-at-a-time loop on the same trace."""
+    arrivals = gen.poisson_arrivals(rate, seconds, args.seed)
+    reqs = [(float(t), k % len(pool)) for k, t in enumerate(arrivals)]
+    log(f"serving: {len(reqs)} requests over {seconds} s at {rate}/s; continuous batching")
+    cb = _serve_continuous(dgs, pool, reqs)
+    log(f"serving: continuous batching: {cb}; plain one-at-a-time loop")
+    plain = _serve_plain(dgs, np, pool, reqs)
+    log(f"serving: plain: {plain}")
+    return {"offered_per_s": round(len(reqs) / seconds, 2), "seconds": seconds, "requests": len(reqs),
+            "continuous_batching": cb, "plain_per_request": plain}
+
+
+def serving_summary(args, dgs, gen, np) -> dict:
+    """The serving workload at its own arrival rate (200/s, more than one GPU
+    completes: the completed rate is then the saturation throughput and the
+    latency is queueing) and at a rate the plain loop also sustains."""
+    pool = serving_pool(args, gen)
+    for A in sorted(pool, key=lambda A: -A.shape[0])[:2]:  # warm the library's caches
+        dgs.solve(A)
+    out = {"n_range": [128, 16384], "pool": len(pool),
+           "note": "requests cycle through a pool of distinct instances"}
+    out["overload_200_per_s"] = run_serving(args, dgs, gen, np, pool, 200.0, args.serve_summary_seconds)
+    out[f"sustained_{int(args.sustained_rate)}_per_s"] = run_serving(args, dgs, gen, np, pool, args.sustained_rate,
+                                                                     args.serve_summary_seconds)
+    return out
 
 
 def main() -> int:
@@ -431,7 +503,14 @@ def main() -> int:
                     help="single-instance workloads: skip the lazy DGS summary")
     ap.add_argument("--no-rect", action="store_true",
                     help="single-instance workloads: skip the rectangular DGS summary")
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="--workload serving: seconds of Poisson arrivals at 200/s")
+    ap.add_argument("--serve-summary-seconds", type=float, default=8.0,
+                    help="single-instance workloads: seconds of arrivals per load of the serving summary")
+    ap.add_argument("--sustained-rate", type=float, default=25.0,
+                    help="single-instance workloads: the serving summary's lower arrival rate (per s)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="single-instance workloads: skip the serving summary")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches): the reference "
                          "kernel that scales the HBM byte counters of a profile")
@@ -478,6 +557,9 @@ def main() -> int:
         if not args.no_batched:
             log("batched workload summary")
             line["batched"] = run_batched(args, dgs, torch, gen, np, steps=3, warmup=1)
+        if not args.no_serving:
+            log("serving summary")
+            line["serving"] = serving_summary(args, dgs, gen, np)
     elif args.workload == "batched512":
         b = run_batched(args, dgs, torch, gen, np, steps=args.steps, warmup=args.warmup)
         config = {"workload": "batched512", "instances": 512, "n": "log-uniform [64, 2048]",
@@ -486,12 +568,17 @@ def main() -> int:
         line["roofline"] = b.pop("roofline")
         line["batched"] = b
     else:
-        s = run_serving(args, dgs, gen, np)
+        pool = serving_pool(args, gen)
+        for A in sorted(pool, key=lambda A: -A.shape[0])[:2]:
+            dgs.solve(A)
+        s = run_serving(args, dgs, gen, np, pool, 200.0, args.serve_seconds)
         config = {"workload": "serving", "arrivals": "Poisson 200/s", "seconds": args.serve_seconds,
-                  "n": "log-uniform [128, 16384]", "generator": "low-rank + noise", "seed": args.seed}
+                  "n": "log-uniform [128, 16384]", "generator": "low-rank + noise", "seed": args.seed,
+                  "pool": len(pool)}
         cb = s["continuous_batching"]
-        line = base_line(args, cb["instances_per_s"], "instances/s",
-                         1000.0 / max(cb["instances_per_s"], 1e-9), config)
+        # a step is one request: its share of the continuous-batching wall time
+        line = base_line(args, cb["completed_per_s"], "instances/s",
+                         1000.0 * cb["wall_s"] / max(cb["requests"], 1), config)
         line["serving"] = s
     print(json.dumps(line), flush=True)
     dgs.release_cached()

@@ -54,7 +54,11 @@ typedef enum dgs_status {
 } dgs_status;
 
 #define DGS_MAX_ABS_BENEFIT 536870911 /* 2^29 - 1 */
-#define DGS_MAX_N 1048576
+/* Largest n of any call.  The default (steepest-ascent) solve, the batched
+ * solve and dgs_solve_rect's m take n <= DGS_MAX_N_SWITCH; DGS_LAZY takes
+ * n <= 16384; DGS_PARALLEL takes n <= DGS_MAX_N.  Larger n: DGS_E_INVAL. */
+#define DGS_MAX_N 262144
+#define DGS_MAX_N_SWITCH 65535
 
 /* dgs_options.flags */
 #define DGS_DEVICE_PTRS 0x1u /* benefit, assign_out, init_assign are device pointers */
@@ -62,16 +66,20 @@ typedef enum dgs_status {
 #define DGS_AUTOTUNE 0x4u    /* batch plans: pick the solver's workgroup size by timing it */
 /* dgs_solve_ex: Parallel DGS (Algorithm 3 with Check Conflicts, Algorithm 4)
  * instead of the steepest-ascent switching loop.  Each round evaluates every
- * agent afresh, walks the agents with a positive best exchange in index
- * order, accepts agent i unless i or i' = sigma(j_i) (the current owner of
- * i's best job j_i) was claimed by an agent accepted before it (an accepted
- * agent claims both), and applies all accepted exchanges at once.  It stops
- * when no agent has a positive best exchange; max_switches then bounds the
- * number of ROUNDS (< 0: no bound).  Ends at a 2-exchange local optimum like
- * the default mode, by another trajectory.  n <= 262144.  In this mode and
- * in DGS_LAZY the switching phase of phase_ms holds every round's (pass's)
- * evaluation, rescans and stalls stay 0, and device_ms also spans the
- * host's read of each round's (pass's) count. */
+ * agent (best exchange, lowest job on ties) and every job (best agent to
+ * take it, its owner taking that agent's job; lowest agent on ties) afresh.
+ * Check Conflicts then looks at the agents with a positive best in index
+ * order, then at the jobs with a positive best in index order; each such
+ * exchange involves two agents (agent i and the current owner of its best
+ * job; job j's best agent and j's current owner) and is kept unless one of
+ * them was claimed by an exchange kept before it (a kept exchange claims
+ * both).  All kept exchanges are applied at once.  It stops when no
+ * exchange improves f; max_switches then bounds the number of ROUNDS (< 0:
+ * no bound).  Ends at a 2-exchange local optimum like the default mode, by
+ * another trajectory.  n <= DGS_MAX_N.  In this mode and in DGS_LAZY the
+ * switching phase of phase_ms holds every round's (pass's) evaluation,
+ * rescans and stalls stay 0, and device_ms also spans the host's read of
+ * each round's (pass's) count. */
 #define DGS_PARALLEL 0x8u
 /* dgs_solve_ex: lazy DGS, Algorithm 1 as printed.  Each pass evaluates every
  * agent (best job, lowest job on ties) and every job (best agent to take it,
@@ -228,7 +236,11 @@ dgs_status dgs_diff_eval(const int32_t *benefit, int32_t n, const int32_t *assig
 typedef struct dgs_server dgs_server;
 
 typedef struct dgs_server_config {
-    uint64_t hbm_budget_bytes; /* device bytes the server may hold for requests (0: 64 GiB) */
+    /* Device bytes the server may hold for requests (0: 64 GiB).  Every
+     * buffer of a request comes from a memory pool the server owns and goes
+     * back to it when the request completes; the pool keeps freed memory for
+     * reuse up to this many bytes. */
+    uint64_t hbm_budget_bytes;
     int32_t max_slots;         /* requests resident on the device at once (0: 64) */
     int32_t max_n;             /* largest accepted n (0: 16384) */
 } dgs_server_config;
@@ -264,6 +276,8 @@ dgs_status dgs_server_poll(dgs_server *s, uint64_t ticket, int32_t *assign_out,
 dgs_status dgs_server_wait(dgs_server *s, uint64_t ticket, int32_t *assign_out,
                            dgs_result *res, int64_t timeout_us);
 
+/* Statistics so far (the statistics call of the boundary; named _get since
+ * the record's typedef already takes the name dgs_server_stats). */
 dgs_status dgs_server_stats_get(dgs_server *s, dgs_server_stats *out);
 
 /* Waits for every queued request, then frees everything. */
@@ -279,9 +293,11 @@ const char *dgs_last_error(void);
 /* Library version string. */
 const char *dgs_version(void);
 
-/* Free the device memory the library caches between calls (workspaces of
- * finished solves).  Safe to call at any time; solves in progress keep
- * their own workspaces.  Later calls allocate again as needed. */
+/* Free the device and pinned host memory and the events the library caches
+ * between calls (workspaces of finished solves, the batched solver's
+ * staging).  Safe to call at any time; solves in progress keep their own
+ * workspaces.  Later calls allocate again as needed.  It also runs at
+ * process exit, before the HIP runtime's own teardown. */
 void dgs_release_cached(void);
 
 #ifdef __cplusplus

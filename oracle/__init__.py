@@ -65,6 +65,8 @@ def lib():
         L.orc_dgs_incr.argtypes = [i32p, ctypes.c_int32, i32p, ctypes.c_int64,
                                    ctypes.POINTER(ctypes.c_int64), i32p, i32p, i64p,
                                    ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        L.orc_set_threads.restype = ctypes.c_int32
+        L.orc_set_threads.argtypes = [ctypes.c_int32]
         L.orc_hungarian.restype = ctypes.c_int64
         L.orc_hungarian.argtypes = [i32p, ctypes.c_int32, i32p]
         _lib = L
@@ -79,6 +81,11 @@ def _mat(A):
     if A.ndim != 2 or A.shape[0] != A.shape[1]:
         raise ValueError("benefit matrix must be square")
     return A
+
+
+def set_threads(k: int) -> int:
+    """OpenMP threads of the C oracle (k > 0); returns the count in effect."""
+    return int(lib().orc_set_threads(int(k)))
 
 
 def objective(A, tau):

@@ -41,6 +41,7 @@
  *       a[i][j] - a[i][tau(i)].  It cannot occur for square inputs; it is
  *       kept so the gain definition is complete.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -50,6 +51,13 @@
 /* a_ij, row-major. */
 static inline int64_t at(const int32_t *A, int64_t n, int64_t i, int64_t j) {
     return (int64_t)A[i * n + j];
+}
+
+/* Threads of the OpenMP loops below (k > 0), for timing the oracle on a
+ * given number of cores; returns the count now in effect. */
+int32_t orc_set_threads(int32_t k) {
+    if (k > 0) omp_set_num_threads(k);
+    return (int32_t)omp_get_max_threads();
 }
 
 /* f(sigma) = sum_i a[i][tau(i)]  (Section 3, objective). */

@@ -43,7 +43,6 @@ void set_error(const char *fmt, ...) {
 struct Context {
     std::once_flag once;
     int device = -1;
-    int loop_grid = 0;
     hipStream_t stream = nullptr;
     dgs_status init_status = DGS_OK;
     std::string init_error;
@@ -52,6 +51,8 @@ struct Context {
 };
 
 Context g_ctx;
+
+void teardown_at_exit();
 
 dgs_status ensure_context() {
     std::call_once(g_ctx.once, [] {
@@ -63,16 +64,14 @@ dgs_status ensure_context() {
             return;
         }
         if (hipGetDevice(&g_ctx.device) != hipSuccess) g_ctx.device = 0;
-        g_ctx.loop_grid = loop_grid_size(g_ctx.device);
-        if (g_ctx.loop_grid < 1) {
-            g_ctx.init_status = DGS_E_DEVICE;
-            g_ctx.init_error = "cannot size the cooperative switch-loop grid";
-            return;
-        }
         if (hipStreamCreateWithFlags(&g_ctx.stream, hipStreamNonBlocking) != hipSuccess) {
             g_ctx.init_status = DGS_E_DEVICE;
             g_ctx.init_error = "hipStreamCreate failed";
+            return;
         }
+        // Registered after the HIP runtime is up, so it runs before the
+        // runtime's own teardown (and before that of tools attached to it).
+        std::atexit(teardown_at_exit);
     });
     if (g_ctx.init_status != DGS_OK) set_error("%s", g_ctx.init_error.c_str());
     return g_ctx.init_status;
@@ -82,33 +81,83 @@ namespace {
 
 // ---- workspaces -----------------------------------------------------------------------
 // One workspace holds the device buffers of one instance of size <= cap.
-// Workspaces are cached (released ones are reused by later calls of a
-// size they fit) so repeated solves do not pay for allocation.
+// By default workspaces are cached (released ones are reused by later calls
+// of a size they fit) so repeated solves do not pay for allocation.  A call
+// that brings a memory pool (the server) takes its buffers from that pool,
+// stream-ordered, and returns them at the end of the call: the pool, not the
+// cache, then bounds the device memory it holds.
 
 struct Workspace {
     int32_t cap = 0;
     bool has_acopy = false;
     int32_t *acopy = nullptr;  // device copy of a host benefit matrix
     int32_t *at = nullptr;
-    int32_t *w = nullptr;
     char *vec = nullptr;  // vectors + scratch
     size_t vec_bytes = 0;
-    int64_t *host_stats = nullptr;  // pinned: stats[8] then flags[4] (as int64)
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t ph[DGS_NUM_PHASES + 1] = {};  // phase boundaries (DGS_PROFILE)
+    hipMemPool_t pool = nullptr;  // buffers from this pool (freed on `stream`), else from hipMalloc
+    hipStream_t stream = nullptr;
 };
 
 std::mutex g_ws_mu;
 std::multimap<int32_t, Workspace *> g_ws_free;
 
+// Host-side resources of a call: a pinned block for the results read back
+// and the timing events.  Cached on their own (freeing pinned memory waits
+// for the whole device), also for calls whose buffers come from a pool.
+struct HostRes {
+    int64_t *stats = nullptr;  // pinned, 16 int64: stats[8], flags[4] (as int64), per-mode scratch
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ph[DGS_NUM_PHASES + 1] = {};  // phase boundaries (DGS_PROFILE)
+};
+
+std::mutex g_host_mu;
+std::vector<HostRes *> g_host_free;
+
+void destroy_host(HostRes *h) {
+    if (!h) return;
+    if (h->stats) (void)hipHostFree(h->stats);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    for (auto &e : h->ph)
+        if (e) (void)hipEventDestroy(e);
+    delete h;
+}
+
+dgs_status acquire_host(HostRes **out) {
+    {
+        std::lock_guard<std::mutex> lk(g_host_mu);
+        if (!g_host_free.empty()) {
+            *out = g_host_free.back();
+            g_host_free.pop_back();
+            return DGS_OK;
+        }
+    }
+    HostRes *h = new HostRes();
+    bool ok = hipHostMalloc((void **)&h->stats, 16 * sizeof(int64_t), hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipEventCreate(&h->ev0) == hipSuccess && hipEventCreate(&h->ev1) == hipSuccess;
+    for (auto &e : h->ph) ok = ok && hipEventCreate(&e) == hipSuccess;
+    if (!ok) {
+        set_error("pinned allocation or hipEventCreate failed");
+        destroy_host(h);
+        return DGS_E_DEVICE;
+    }
+    *out = h;
+    return DGS_OK;
+}
+
+void release_host(HostRes *h) {
+    std::lock_guard<std::mutex> lk(g_host_mu);
+    g_host_free.push_back(h);
+}
+
 // Byte layout of the vector block of a workspace.  Every piece starts on a
 // 256-byte boundary; vec_layout() is the single source of the offsets used
 // both to size the allocation and to carve it.
 struct VecLayout {
-    size_t tau, sigma, d, bc, bk, bb, lists, recs, barrier, stats, flags, words, greedy, scan, par, total;
+    size_t tau, sigma, d, bc, bk, bb, lists, stats, flags, words, greedy, scan, par, total;
 };
 
-VecLayout vec_layout(int32_t n, int grid) {
+VecLayout vec_layout(int32_t n) {
     VecLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -123,8 +172,6 @@ VecLayout vec_layout(int32_t n, int grid) {
     L.bk = take((size_t)n * 8);
     L.bb = take((size_t)n * 8);
     L.lists = take((size_t)n * 8 * kScanListLen);
-    L.recs = take(2 * (size_t)grid * loop_record_bytes());
-    L.barrier = take(256);
     L.stats = take(8 * sizeof(int64_t));
     L.flags = take(4 * sizeof(int32_t));
     const bool ex = n >= 2 && n <= kSwitchExMaxN;
@@ -138,20 +185,20 @@ VecLayout vec_layout(int32_t n, int grid) {
 
 void free_ws(Workspace *w) {
     if (!w) return;
-    if (w->acopy) (void)hipFree(w->acopy);
-    if (w->at) (void)hipFree(w->at);
-    if (w->w) (void)hipFree(w->w);
-    if (w->vec) (void)hipFree(w->vec);
-    if (w->host_stats) (void)hipHostFree(w->host_stats);
-    if (w->ev0) (void)hipEventDestroy(w->ev0);
-    if (w->ev1) (void)hipEventDestroy(w->ev1);
-    for (auto &e : w->ph)
-        if (e) (void)hipEventDestroy(e);
+    for (void *p : {(void *)w->acopy, (void *)w->at, (void *)w->vec}) {
+        if (!p) continue;
+        if (w->pool)
+            (void)hipFreeAsync(p, w->stream);
+        else
+            (void)hipFree(p);
+    }
     delete w;
 }
 
-dgs_status alloc_ws(int32_t n, bool need_acopy, Workspace **out) {
-    {
+// Device buffers for an instance of size n: from the cache (pool == NULL)
+// or from `pool`, ordered on `stream`.
+dgs_status alloc_ws(int32_t n, bool need_acopy, hipMemPool_t pool, hipStream_t stream, Workspace **out) {
+    if (!pool) {
         std::lock_guard<std::mutex> lk(g_ws_mu);
         for (auto it = g_ws_free.lower_bound(n); it != g_ws_free.end(); ++it) {
             // do not hand a huge workspace to a tiny problem
@@ -164,46 +211,45 @@ dgs_status alloc_ws(int32_t n, bool need_acopy, Workspace **out) {
     }
     Workspace *w = new Workspace();
     w->cap = n;
+    w->pool = pool;
+    w->stream = stream;
     const size_t mat = (size_t)n * (size_t)n * sizeof(int32_t);
+    auto dev = [&](void **p, size_t bytes) {
+        return (pool ? hipMallocFromPoolAsync(p, bytes, pool, stream) : hipMalloc(p, bytes)) == hipSuccess;
+    };
     auto fail = [&](const char *what) {
         set_error("device allocation of %s for n=%d failed", what, n);
         free_ws(w);
         return DGS_E_NOMEM;
     };
     if (need_acopy) {
-        if (hipMalloc((void **)&w->acopy, mat) != hipSuccess) return fail("benefit copy");
+        if (!dev((void **)&w->acopy, mat)) return fail("benefit copy");
         w->has_acopy = true;
     }
-    if (hipMalloc((void **)&w->at, mat) != hipSuccess) return fail("transpose");
-    if (hipMalloc((void **)&w->w, mat) != hipSuccess) return fail("working matrix");
-    w->vec_bytes = vec_layout(n, g_ctx.loop_grid).total;
-    if (hipMalloc((void **)&w->vec, w->vec_bytes) != hipSuccess) return fail("vectors");
-    if (hipHostMalloc((void **)&w->host_stats, 16 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
-        return fail("pinned stats");
-    bool ev_ok = hipEventCreate(&w->ev0) == hipSuccess && hipEventCreate(&w->ev1) == hipSuccess;
-    for (auto &e : w->ph) ev_ok = ev_ok && hipEventCreate(&e) == hipSuccess;
-    if (!ev_ok) {
-        set_error("hipEventCreate failed");
-        free_ws(w);
-        return DGS_E_DEVICE;
-    }
+    if (!dev((void **)&w->at, mat)) return fail("transpose");
+    w->vec_bytes = vec_layout(n).total;
+    if (!dev((void **)&w->vec, w->vec_bytes)) return fail("vectors");
     *out = w;
     return DGS_OK;
 }
 
+// Back to the cache, or (pool buffers) back to the pool.
 void release_ws(Workspace *w) {
+    if (w->pool) {
+        free_ws(w);
+        return;
+    }
     std::lock_guard<std::mutex> lk(g_ws_mu);
     g_ws_free.emplace(w->cap, w);
 }
 
-// Carve an Instance out of a workspace (n <= w->cap, grid <= loop grid).
-Instance carve(Workspace *w, const int32_t *A, int32_t n, int grid) {
+// Carve an Instance out of a workspace (n <= w->cap).
+Instance carve(Workspace *w, const int32_t *A, int32_t n) {
     Instance I;
     I.n = n;
     I.A = A;
     I.AT = w->at;
-    I.W = w->w;
-    const VecLayout L = vec_layout(n, grid);
+    const VecLayout L = vec_layout(n);
     char *p = w->vec;
     I.tau = (int32_t *)(p + L.tau);
     I.sigma = (int32_t *)(p + L.sigma);
@@ -212,8 +258,6 @@ Instance carve(Workspace *w, const int32_t *A, int32_t n, int grid) {
     I.bk = (u64 *)(p + L.bk);
     I.bb = (u64 *)(p + L.bb);
     I.lists = (u64 *)(p + L.lists);
-    I.recs = p + L.recs;
-    I.barrier = (uint32_t *)(p + L.barrier);
     I.stats = (int64_t *)(p + L.stats);
     I.flags = (int32_t *)(p + L.flags);
     I.words = p + L.words;
@@ -261,16 +305,18 @@ struct Call {
     bool coop = true;  // cooperative switching launch (else the caller owns co-residency)
     bool parallel = false;  // Parallel DGS rounds instead of the switching loop (max_switches = max rounds)
     bool lazy = false;      // lazy DGS passes (Algorithm 1 as printed) instead of the switching loop
+    hipMemPool_t pool = nullptr;  // device buffers from this pool (stream-ordered) instead of the cache
     hipStream_t stream;
 };
 
 // Parallel DGS (Algorithm 3): rounds of Check Conflicts + apply, each
-// followed by a fresh difference evaluation, until a round accepts nothing.
-// Expects the evaluation of the start assignment in I.bk / I.bc.  The
+// followed by a fresh difference evaluation of every agent and every job,
+// until a round keeps nothing.  Expects the evaluation of the start
+// assignment in I.bk / I.bc (agents) and I.bb (jobs, per owner agent).  The
 // evaluations read A^T through tau, so W is never built.
-dgs_status parallel_rounds(const Instance &I, Workspace *w, int64_t max_rounds, int64_t *rounds_out, hipStream_t s) {
+dgs_status parallel_rounds(const Instance &I, HostRes *h, int64_t max_rounds, int64_t *rounds_out, hipStream_t s) {
     int64_t rounds = 0;
-    int64_t *accepted = w->host_stats + 12;
+    int64_t *accepted = h->stats + 12;
     while (max_rounds < 0 || rounds < max_rounds) {
         DGS_HIP(launch_parallel_round(I, I.par, s));
         DGS_HIP(hipMemcpyAsync(accepted, I.stats + 5, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -280,7 +326,7 @@ dgs_status parallel_rounds(const Instance &I, Workspace *w, int64_t max_rounds, 
         if (max_rounds >= 0 && rounds >= max_rounds) break;
         // fresh d and evaluation; stats[6] takes the objective sum (f0 stays the start's)
         DGS_HIP(launch_benefits(I.A, I.tau, I.n, I.d, I.stats + 6, s));
-        DGS_HIP(launch_scan_best_transposed(I, I.scan, s));
+        DGS_HIP(launch_scan_best_transposed(I, I.scan, s, I.bk, I.bc, I.bb));
     }
     *rounds_out = rounds;
     return DGS_OK;
@@ -290,15 +336,14 @@ dgs_status parallel_rounds(const Instance &I, Workspace *w, int64_t max_rounds, 
 // (into I.bk) and jobs (per owner agent, into I.bb, free in this mode)
 // followed by the single-workgroup switching phase, until a pass applies
 // nothing or max_switches is reached.  d must be current; the passes keep it.
-dgs_status lazy_passes(const Instance &I, Workspace *w, int64_t max_switches, int64_t *passes_out, hipStream_t s) {
+dgs_status lazy_passes(const Instance &I, HostRes *h, int64_t max_switches, int64_t *passes_out, hipStream_t s) {
     int64_t passes = 0, S = 0;
-    int64_t *hs = w->host_stats + 10;  // [0..5] = stats[0..5]
+    int64_t *hs = h->stats + 10;  // [0..5] = stats[0..5]
     while (max_switches < 0 || S < max_switches) {
-        DGS_HIP(launch_scan_best_transposed(I, I.scan, s, false, I.bk, nullptr));
-        DGS_HIP(launch_scan_best_transposed(I, I.scan, s, true, I.bb, nullptr));
+        DGS_HIP(launch_scan_best_transposed(I, I.scan, s, I.bk, nullptr, I.bb));
         ++passes;
         DGS_HIP(launch_lazy_pass(I, I.bb, max_switches, s));
-        int32_t *err = (int32_t *)(w->host_stats + 9);  // rewritten by the final flags copy
+        int32_t *err = (int32_t *)(h->stats + 9);  // rewritten by the final flags copy
         DGS_HIP(hipMemcpyAsync(hs, I.stats, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
         DGS_HIP(hipMemcpyAsync(err, I.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         DGS_HIP(hipStreamSynchronize(s));
@@ -318,6 +363,11 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         set_error("parallel mode supports n <= %d", parallel_max_agents());
         return DGS_E_INVAL;
     }
+    if (!c.parallel && !c.lazy && mode == Mode::Solve && n > kSwitchExMaxN) {
+        set_error("the steepest-ascent solve supports n <= %d (DGS_PARALLEL: n <= %d)", kSwitchExMaxN,
+                  parallel_max_agents());
+        return DGS_E_INVAL;
+    }
     if (c.lazy && (c.parallel || n > kLazyMaxN)) {
         set_error(c.parallel ? "DGS_LAZY and DGS_PARALLEL exclude each other" : "lazy mode supports n <= %d",
                   kLazyMaxN);
@@ -327,29 +377,38 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         dgs_status st = check_init(c.assign_in, n, c.dev, s);
         if (st != DGS_OK) return st;
     }
-    Workspace *w = nullptr;
-    dgs_status st = alloc_ws(n, !c.dev, &w);
+    HostRes *h = nullptr;
+    dgs_status st = acquire_host(&h);
     if (st != DGS_OK) return st;
+    Workspace *w = nullptr;
+    st = alloc_ws(n, !c.dev, c.pool, s, &w);
+    if (st != DGS_OK) {
+        release_host(h);
+        return st;
+    }
     struct Guard {
         Workspace *w;
-        ~Guard() { release_ws(w); }
-    } guard{w};
+        HostRes *h;
+        ~Guard() {
+            release_ws(w);
+            release_host(h);
+        }
+    } guard{w, h};
 
-    const int grid = std::max(1, std::min(g_ctx.loop_grid, (int)n));
-    if (vec_layout(n, grid).total > w->vec_bytes) {
+    if (vec_layout(n).total > w->vec_bytes) {
         set_error("internal: workspace too small for n=%d", n);
         return DGS_E_NOMEM;
     }
     const int32_t *A = c.dev ? c.benefit : w->acopy;
-    Instance I = carve(w, A, n, grid);
+    Instance I = carve(w, A, n);
     const size_t mat = (size_t)n * (size_t)n * sizeof(int32_t);
     if (!c.dev) DGS_HIP(hipMemcpyAsync(w->acopy, c.benefit, mat, hipMemcpyHostToDevice, s));
 
-    DGS_HIP(hipEventRecord(w->ev0, s));
-    auto mark = [&](int i) { return c.profile ? hipEventRecord(w->ph[i], s) : hipSuccess; };
-    DGS_HIP(hipMemsetAsync(I.barrier, 0, 256, s));
-    DGS_HIP(hipMemsetAsync(I.stats, 0, 8 * sizeof(int64_t), s));
-    DGS_HIP(hipMemsetAsync(I.flags, 0, 4 * sizeof(int32_t), s));
+    DGS_HIP(hipEventRecord(h->ev0, s));
+    auto mark = [&](int i) { return c.profile ? hipEventRecord(h->ph[i], s) : hipSuccess; };
+    // cleared by kernels (no memset nodes if a caller captures the stream)
+    DGS_HIP(launch_fill((int32_t *)I.stats, 16, 0, s));
+    DGS_HIP(launch_fill(I.flags, 4, 0, s));
     DGS_HIP(mark(DGS_PHASE_RANGE));
     DGS_HIP(launch_range_check(A, (int64_t)n * n, I.flags, s));
     DGS_HIP(mark(DGS_PHASE_INIT));
@@ -362,23 +421,19 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     }
     DGS_HIP(mark(DGS_PHASE_LAYOUT));
     DGS_HIP(launch_transpose(A, I.AT, n, s));
-    const bool no_w = (c.parallel || c.lazy) && mode == Mode::Solve;  // these modes evaluate from AT
-    if (no_w)
-        DGS_HIP(launch_benefits(A, I.tau, n, I.d, I.stats + 2, s));
-    else
-        DGS_HIP(launch_build_w(A, I.AT, I.tau, n, I.W, I.d, I.stats + 2, s));
+    DGS_HIP(launch_benefits(A, I.tau, n, I.d, I.stats + 2, s));
     DGS_HIP(mark(DGS_PHASE_SCAN));
     if (c.parallel && mode == Mode::Solve)
-        DGS_HIP(launch_scan_best_transposed(I, I.scan, s));
-    else if (!no_w)
+        DGS_HIP(launch_scan_best_transposed(I, I.scan, s, I.bk, I.bc, I.bb));
+    else if (!c.lazy || mode != Mode::Solve)
         DGS_HIP(launch_scan_pairs(I, I.scan, s));  // (lazy passes evaluate at their start)
     DGS_HIP(mark(DGS_PHASE_SWITCH));
     int64_t rounds = 0;
     if (mode == Mode::Solve && c.parallel) {
-        st = parallel_rounds(I, w, c.max_switches, &rounds, s);
+        st = parallel_rounds(I, h, c.max_switches, &rounds, s);
         if (st != DGS_OK) return st;
     } else if (mode == Mode::Solve && c.lazy) {
-        st = lazy_passes(I, w, c.max_switches, &rounds, s);
+        st = lazy_passes(I, h, c.max_switches, &rounds, s);
         if (st != DGS_OK) return st;
     } else if (mode == Mode::Solve) {
         // The loops exit at once when the range check failed.  n = 1 has no
@@ -386,26 +441,24 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         // run one at a time (each needs its whole grid resident).
         std::unique_lock<std::mutex> lk(g_ctx.loop_mu, std::defer_lock);
         if (c.coop) lk.lock();
-        if (n >= 2 && n <= kSwitchExMaxN) {
+        if (n >= 2) {
             // stale round tags must not match rounds 0 and 1
-            DGS_HIP(hipMemsetAsync(I.words, 0xFF, switch_v3_word_bytes(n), s));
+            DGS_HIP(launch_fill((int32_t *)I.words, (int32_t)(switch_v3_word_bytes(n) / 4), -1, s));
             DGS_HIP(launch_switch_v3(I, c.max_switches, I.words, I.flags + 2, c.coop, s));
-        } else if (n > kSwitchExMaxN) {
-            DGS_HIP(launch_switch_loop(I, c.max_switches, grid, s));
         }
         if (c.coop) {
-            DGS_HIP(hipEventRecord(w->ev1, s));
-            DGS_HIP(hipEventSynchronize(w->ev1));
+            DGS_HIP(hipEventRecord(h->ev1, s));
+            DGS_HIP(hipEventSynchronize(h->ev1));
         }
     } else {
         DGS_HIP(launch_export_best(I, gain_out, job_out, s));
     }
     DGS_HIP(mark(DGS_NUM_PHASES));
-    DGS_HIP(hipEventRecord(w->ev1, s));
-    DGS_HIP(hipMemcpyAsync(w->host_stats, I.stats, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    DGS_HIP(hipMemcpyAsync(w->host_stats + 8, I.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DGS_HIP(hipEventRecord(h->ev1, s));
+    DGS_HIP(hipMemcpyAsync(h->stats, I.stats, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DGS_HIP(hipMemcpyAsync(h->stats + 8, I.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DGS_HIP(hipStreamSynchronize(s));
-    const int32_t *flags = (const int32_t *)(w->host_stats + 8);
+    const int32_t *flags = (const int32_t *)(h->stats + 8);
     if (flags[0]) {
         set_error("benefit entry outside [-(2^29-1), 2^29-1]");
         return DGS_E_RANGE;
@@ -425,8 +478,8 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     }
     if (res) {
         float ms = 0.f;
-        DGS_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-        const int64_t *hs = w->host_stats;
+        DGS_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        const int64_t *hs = h->stats;
         res->initial_benefit = hs[2];
         res->total_benefit = hs[2] + hs[1];
         res->switches = hs[0];
@@ -437,7 +490,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         res->device_ms = ms;
         for (int i = 0; i < DGS_NUM_PHASES; ++i) {
             float pm = 0.f;
-            if (c.profile) DGS_HIP(hipEventElapsedTime(&pm, w->ph[i], w->ph[i + 1]));
+            if (c.profile) DGS_HIP(hipEventElapsedTime(&pm, h->ph[i], h->ph[i + 1]));
             res->phase_ms[i] = pm;
         }
     }
@@ -459,44 +512,40 @@ struct BatchCall {
     bool dev;
     bool profile;
     int grid_cap = 0;  // > 0: at most this many workgroups (the server reserves the rest)
+    hipMemPool_t pool = nullptr;  // device buffers from this pool per call (else the arena's cached block)
+    BatchArena *arena = nullptr;  // host staging and events (else the library's own arena)
     hipStream_t stream;
 };
 
-struct BatchArena {
-    std::mutex mu;
-    char *dev = nullptr;
-    size_t bytes = 0;
-    char *host = nullptr;  // pinned staging for items / order / results
-    size_t host_bytes = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-};
 BatchArena g_batch;
 
 int g_batch_block = 256;  // workgroup size of the batched solver (autotuned)
 
-dgs_status batch_reserve(size_t dev_bytes, size_t host_bytes) {
-    if (dev_bytes > g_batch.bytes) {
-        if (g_batch.dev) (void)hipFree(g_batch.dev);
-        g_batch.dev = nullptr;
-        g_batch.bytes = 0;
-        if (hipMalloc((void **)&g_batch.dev, dev_bytes) != hipSuccess) {
+// Host staging and events of the arena; its cached device block too unless
+// the call brings a pool.
+dgs_status batch_reserve(BatchArena &A, size_t dev_bytes, size_t host_bytes, bool cache_dev) {
+    if (cache_dev && dev_bytes > A.bytes) {
+        if (A.dev) (void)hipFree(A.dev);
+        A.dev = nullptr;
+        A.bytes = 0;
+        if (hipMalloc((void **)&A.dev, dev_bytes) != hipSuccess) {
             set_error("device allocation of %zu bytes for a batch failed", dev_bytes);
             return DGS_E_NOMEM;
         }
-        g_batch.bytes = dev_bytes;
+        A.bytes = dev_bytes;
     }
-    if (host_bytes > g_batch.host_bytes) {
-        if (g_batch.host) (void)hipHostFree(g_batch.host);
-        g_batch.host = nullptr;
-        g_batch.host_bytes = 0;
-        if (hipHostMalloc((void **)&g_batch.host, host_bytes, hipHostMallocDefault) != hipSuccess) {
+    if (host_bytes > A.host_bytes) {
+        if (A.host) (void)hipHostFree(A.host);
+        A.host = nullptr;
+        A.host_bytes = 0;
+        if (hipHostMalloc((void **)&A.host, host_bytes, hipHostMallocDefault) != hipSuccess) {
             set_error("pinned allocation of %zu bytes for a batch failed", host_bytes);
             return DGS_E_NOMEM;
         }
-        g_batch.host_bytes = host_bytes;
+        A.host_bytes = host_bytes;
     }
-    if (!g_batch.ev0) {
-        if (hipEventCreate(&g_batch.ev0) != hipSuccess || hipEventCreate(&g_batch.ev1) != hipSuccess) {
+    if (!A.ev0) {
+        if (hipEventCreate(&A.ev0) != hipSuccess || hipEventCreate(&A.ev1) != hipSuccess) {
             set_error("hipEventCreate failed");
             return DGS_E_DEVICE;
         }
@@ -512,7 +561,8 @@ dgs_status run_batch(const BatchCall &c) {
     std::stable_sort(small.begin(), small.end(), [&](int32_t x, int32_t y) { return c.ns[x] > c.ns[y]; });
     const size_t m = small.size();
     if (m) {
-        std::lock_guard<std::mutex> lk(g_batch.mu);
+        BatchArena &arena = c.arena ? *c.arena : g_batch;
+        std::lock_guard<std::mutex> lk(arena.mu);
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
         size_t mat = 0, vec = 0;
         for (int32_t b : small) {
@@ -524,9 +574,22 @@ dgs_status run_batch(const BatchCall &c) {
         const size_t items_b = al(m * sizeof(BatchItem)), order_b = al(m * 4), res_b = al(m * 5 * 8);
         const size_t dev_bytes = (c.dev ? 0 : mat) + mat + lists + (c.dev ? 0 : vec) + items_b + order_b + res_b + 256;
         const size_t host_bytes = items_b + order_b + res_b;
-        dgs_status st = batch_reserve(dev_bytes, host_bytes);
+        dgs_status st = batch_reserve(arena, dev_bytes, host_bytes, !c.pool);
         if (st != DGS_OK) return st;
-        char *p = g_batch.dev;
+        char *block = arena.dev;
+        if (c.pool && hipMallocFromPoolAsync((void **)&block, dev_bytes, c.pool, s) != hipSuccess) {
+            set_error("device allocation of %zu bytes for a batch failed", dev_bytes);
+            return DGS_E_NOMEM;
+        }
+        struct PoolBlock {
+            char *p;
+            hipStream_t s;
+            bool pooled;
+            ~PoolBlock() {
+                if (pooled) (void)hipFreeAsync(p, s);
+            }
+        } pool_block{block, s, c.pool != nullptr};
+        char *p = block;
         char *acopy = nullptr, *tauo = nullptr;
         if (!c.dev) {
             acopy = p;
@@ -547,9 +610,9 @@ dgs_status run_batch(const BatchCall &c) {
         int64_t *d_res = (int64_t *)p;
         p += res_b;
         int32_t *d_queue = (int32_t *)p;
-        BatchItem *h_items = (BatchItem *)g_batch.host;
-        int32_t *h_order = (int32_t *)(g_batch.host + items_b);
-        int64_t *h_res = (int64_t *)(g_batch.host + items_b + order_b);
+        BatchItem *h_items = (BatchItem *)arena.host;
+        int32_t *h_order = (int32_t *)(arena.host + items_b);
+        int64_t *h_res = (int64_t *)(arena.host + items_b + order_b);
         size_t om = 0, ov = 0, ol = 0;
         for (size_t x = 0; x < m; ++x) {
             const int32_t b = small[x];
@@ -575,7 +638,7 @@ dgs_status run_batch(const BatchCall &c) {
         }
         DGS_HIP(hipMemcpyAsync(d_items, h_items, m * sizeof(BatchItem), hipMemcpyHostToDevice, s));
         DGS_HIP(hipMemcpyAsync(d_order, h_order, m * 4, hipMemcpyHostToDevice, s));
-        DGS_HIP(hipMemsetAsync(d_queue, 0, 4, s));
+        DGS_HIP(launch_fill(d_queue, 1, 0, s));
         const int limit = batch_grid_limit(g_batch_block);
         if (limit < 1) {
             set_error("cannot size the batched solver's grid");
@@ -583,9 +646,9 @@ dgs_status run_batch(const BatchCall &c) {
         }
         int grid = (int)std::min<size_t>(m, (size_t)limit);
         if (c.grid_cap > 0) grid = std::min(grid, c.grid_cap);
-        DGS_HIP(hipEventRecord(g_batch.ev0, s));
+        DGS_HIP(hipEventRecord(arena.ev0, s));
         DGS_HIP(launch_batch(d_items, d_order, (int)m, d_queue, c.max_switches, g_batch_block, grid, s));
-        DGS_HIP(hipEventRecord(g_batch.ev1, s));
+        DGS_HIP(hipEventRecord(arena.ev1, s));
         DGS_HIP(hipMemcpyAsync(h_res, d_res, m * 5 * 8, hipMemcpyDeviceToHost, s));
         DGS_HIP(hipStreamSynchronize(s));
         for (size_t x = 0; x < m; ++x) {
@@ -595,7 +658,7 @@ dgs_status run_batch(const BatchCall &c) {
             }
         }
         float ms = 0.f;
-        DGS_HIP(hipEventElapsedTime(&ms, g_batch.ev0, g_batch.ev1));
+        DGS_HIP(hipEventElapsedTime(&ms, arena.ev0, arena.ev1));
         if (!c.dev) {
             size_t ov2 = 0;
             for (size_t x = 0; x < m; ++x) {
@@ -625,6 +688,7 @@ dgs_status run_batch(const BatchCall &c) {
         one.max_switches = c.max_switches;
         one.dev = c.dev;
         one.profile = c.profile;
+        one.pool = c.pool;
         one.stream = s;
         dgs_status st = run_instance(one, Mode::Solve, c.outs[b], nullptr, nullptr,
                                      c.results ? &c.results[b] : nullptr);
@@ -647,10 +711,19 @@ dgs_status check_common(const int32_t *benefit, int32_t n, const void *out) {
 
 }  // namespace
 
+void batch_arena_clear(BatchArena &A) {
+    if (A.dev) (void)hipFree(A.dev);
+    if (A.host) (void)hipHostFree(A.host);
+    if (A.ev0) (void)hipEventDestroy(A.ev0);
+    if (A.ev1) (void)hipEventDestroy(A.ev1);
+    A.dev = A.host = nullptr;
+    A.bytes = A.host_bytes = 0;
+    A.ev0 = A.ev1 = nullptr;
+}
+
 int switch_loop_grid(int n) {
     if (n < 2) return 0;
-    if (n > kSwitchExMaxN) return g_ctx.loop_grid;
-    return switch_v3_grid(n);
+    return switch_v3_grid(std::min(n, kSwitchExMaxN));
 }
 
 int device_cus() {
@@ -661,7 +734,7 @@ int device_cus() {
 }
 
 dgs_status solve_internal(const int32_t *benefit, int32_t n, int32_t *assign_out, int64_t max_switches, bool dev,
-                          bool coop, hipStream_t s, dgs_result *res) {
+                          bool coop, hipStream_t s, dgs_result *res, hipMemPool_t pool) {
     dgs_status st = check_common(benefit, n, assign_out);
     if (st != DGS_OK) return st;
     if ((st = ensure_context()) != DGS_OK) return st;
@@ -673,13 +746,14 @@ dgs_status solve_internal(const int32_t *benefit, int32_t n, int32_t *assign_out
     c.dev = dev;
     c.profile = false;
     c.coop = coop;
+    c.pool = pool;
     c.stream = s ? s : g_ctx.stream;
     return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
 }
 
 dgs_status solve_batch_internal(int32_t count, const int32_t *const *benefits, const int32_t *ns,
                                 int32_t *const *outs, dgs_result *results, int64_t max_switches, int grid_cap,
-                                hipStream_t s) {
+                                hipStream_t s, hipMemPool_t pool, BatchArena *arena) {
     dgs_status st = ensure_context();
     if (st != DGS_OK) return st;
     BatchCall c;
@@ -692,8 +766,25 @@ dgs_status solve_batch_internal(int32_t count, const int32_t *const *benefits, c
     c.dev = false;
     c.profile = false;
     c.grid_cap = grid_cap;
+    c.pool = pool;
+    c.arena = arena;
     c.stream = s ? s : g_ctx.stream;
     return run_batch(c);
+}
+
+// At process exit: give back everything the library still holds (cached
+// workspaces, host resources, the batch arena) and its stream, while the HIP
+// runtime is still up.  Batch plans and servers belong to the caller, who
+// destroys them.
+void teardown_at_exit() {
+    dgs_release_cached();
+    if (g_ctx.stream) {
+        (void)hipStreamSynchronize(g_ctx.stream);
+        (void)hipStreamDestroy(g_ctx.stream);
+        g_ctx.stream = nullptr;
+    }
+    g_ctx.init_status = DGS_E_DEVICE;
+    g_ctx.init_error = "the library has been shut down (process exit)";
 }
 
 }  // namespace dgs
@@ -725,12 +816,14 @@ void dgs_release_cached(void) {
         drop.swap(g_ws_free);
     }
     for (auto &kv : drop) free_ws(kv.second);
+    std::vector<HostRes *> hosts;
+    {
+        std::lock_guard<std::mutex> lk(g_host_mu);
+        hosts.swap(g_host_free);
+    }
+    for (HostRes *h : hosts) destroy_host(h);
     std::lock_guard<std::mutex> lk(g_batch.mu);
-    if (g_batch.dev) (void)hipFree(g_batch.dev);
-    if (g_batch.host) (void)hipHostFree(g_batch.host);
-    g_batch.dev = nullptr;
-    g_batch.host = nullptr;
-    g_batch.bytes = g_batch.host_bytes = 0;
+    batch_arena_clear(g_batch);
 }
 
 dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out, const dgs_options *opt,

@@ -297,7 +297,7 @@ hipError_t launch_greedy_rounds(const int32_t *A, int32_t n, int32_t *tau, int32
     u64 *lists = (u64 *)scratch;
     uint32_t *taken = (uint32_t *)((char *)scratch + (size_t)kRound * 64 * sizeof(u64));
     const int words = (n + 31) / 32;
-    hipError_t e = hipMemsetAsync(taken, 0, (size_t)words * 4, s);
+    hipError_t e = launch_fill((int32_t *)taken, words, 0, s);
     if (e != hipSuccess) return e;
     const size_t rshm = (size_t)kRound * 64 * sizeof(u64) + (size_t)words * 4;
     e = hipFuncSetAttribute((const void *)k_greedy_resolve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rshm);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/dgs.h"
 
 namespace dgs {
@@ -14,12 +16,13 @@ typedef unsigned long long u64;
 // Device state of one single-instance solve.  Layout (all row-major int32,
 // n x n, 64-bit element offsets):
 //   A   the caller's benefit matrix a_ij (read-only)
-//   AT  its transpose: AT[j][i] = a_ij (read-only after the build)
-//   W   the assignment-ordered matrix W[r][c] = a[r][tau(c)]: the benefit
-//       agent r would get from agent c's current job.  Kept current across
-//       switches (two entries per row change per switch).
+//   AT  its transpose: AT[j][i] = a_ij (read-only after the build).  Row
+//       tau(c) of AT is column c of the assignment-ordered matrix
+//       W[r][c] = a[r][tau(c)] (the benefit agent r would get from agent c's
+//       current job), which the evaluation reads this way; W itself is
+//       never built.
 // Vectors (n entries): tau (job of agent), sigma (agent of job), d (current
-// benefit of agent c, d[c] = W[c][c]).
+// benefit of agent c, d[c] = a[c][tau(c)]).
 // Per-agent best record: bk = packed key of the best exchange (gain, job),
 // bb = bound key (every other exchange of the agent is <= bb), bc = the
 // partner agent of the best exchange.
@@ -30,7 +33,6 @@ struct Instance {
     int32_t n = 0;
     const int32_t *A = nullptr;
     int32_t *AT = nullptr;
-    int32_t *W = nullptr;
     int32_t *tau = nullptr;
     int32_t *sigma = nullptr;
     int32_t *d = nullptr;
@@ -38,8 +40,6 @@ struct Instance {
     u64 *bb = nullptr;
     int32_t *bc = nullptr;
     // scratch for the switch loop and small reductions
-    void *recs = nullptr;        // 2 x grid records
-    uint32_t *barrier = nullptr; // grid barrier counter
     int64_t *stats = nullptr;    // [0] switches, [1] gain sum, [2] f0, [3] re-evaluations, [4] stalls,
                                  // [5] accepted in the last parallel round, [6] scratch sum
     int32_t *flags = nullptr;    // [0] range error, [1] permutation error, [2] wait timed out
@@ -64,12 +64,7 @@ dgs_status ensure_context();            // device, stream and switch-loop grid, 
         }                                                                                   \
     } while (0)
 
-size_t loop_record_bytes();
-int loop_grid_size(int device);
-
 hipError_t launch_range_check(const int32_t *A, int64_t count, int32_t *flag, hipStream_t s);
-hipError_t launch_greedy(const int32_t *A, int32_t n, int32_t *tau, int32_t *sigma,
-                         hipStream_t s);
 // Greedy start in rounds (dgs_greedy.hip); scratch of greedy_scratch_bytes(n).
 size_t greedy_scratch_bytes(int n);
 hipError_t launch_greedy_rounds(const int32_t *A, int32_t n, int32_t *tau, int32_t *sigma, void *scratch,
@@ -79,23 +74,22 @@ hipError_t launch_fill(int32_t *p, int32_t n, int32_t v, hipStream_t s);
 hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, int32_t *flag,
                                  hipStream_t s);
 hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t n, hipStream_t s);
-// W from AT (built first) and tau; d and f0 from A.
-hipError_t launch_build_w(const int32_t *A, const int32_t *AT, const int32_t *tau, int32_t n, int32_t *W,
-                          int32_t *d, int64_t *f0, hipStream_t s);
-// d and the objective sum alone (W left as it is).
+// d[r] = a[r][tau(r)] and the objective sum.
 hipError_t launch_benefits(const int32_t *A, const int32_t *tau, int32_t n, int32_t *d, int64_t *f, hipStream_t s);
-hipError_t launch_scan_rows(const Instance &I, hipStream_t s);
-// Symmetric tile-pair difference evaluation (dgs_scan.hip).
+// Symmetric tile-pair difference evaluation from A^T through tau
+// (dgs_scan.hip): each agent's best exchange into I.bk / I.bc, its candidate
+// list into I.lists and the list's bound into I.bb.
 size_t scan_pairs_scratch_bytes(int n);
 hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s);
-// The same evaluation read from A^T through tau (W need not be built), writing
-// only each agent's best: into I.bk / I.bc (best == nullptr), else into best
-// (and partner, if not null).  by_agent keys each candidate by the partner
-// agent instead of its job (the best agent to take the agent's job).
-hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s, bool by_agent = false,
-                                       u64 *best = nullptr, int32_t *partner = nullptr);
-hipError_t launch_switch_loop(const Instance &I, int64_t max_switches, int grid, hipStream_t s);
-// Largest n of the switching loop with cooperative re-evaluation (16-bit agent and job fields).
+// The same evaluation, in one pass writing each agent's best keyed by job
+// into by_job (its partner
+// sigma(job) into partner, if not null: the agent side, ADE) and its best
+// keyed by partner agent into by_agent (the best agent to take the agent's
+// job, lowest agent on ties: the job side, JDE, of job tau(agent)).
+hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s, u64 *by_job,
+                                       int32_t *partner, u64 *by_agent);
+// Largest n of the switching loop with cooperative re-evaluation (16-bit agent
+// and job fields): the largest n of the steepest-ascent solve.
 constexpr int kSwitchExMaxN = 65535;
 // Switching loop with cooperative re-evaluation (dgs_switch3.hip), for 2 <= n <= kSwitchExMaxN:
 // grid of switch_v3_grid(n) workgroups, exchange words of switch_v3_word_bytes(n) (set to 0xFF first).
@@ -106,12 +100,28 @@ hipError_t launch_switch_v3(const Instance &I, int64_t max_switches, void *words
 // Workgroups the switching loop of an n-agent solve keeps resident.
 int switch_loop_grid(int n);
 
-// Internal entry points used by the server (dgs_api.cpp).
+// Host staging (pinned), timing events and, for calls without a memory
+// pool, a cached device block of the batched solver.  The library keeps one
+// for its own calls; the server's small-request worker owns another.
+struct BatchArena {
+    std::mutex mu;
+    char *dev = nullptr;
+    size_t bytes = 0;
+    char *host = nullptr;  // pinned staging for items / order / results
+    size_t host_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+// Frees what the arena holds (device block, pinned staging, events).
+void batch_arena_clear(BatchArena &A);
+
+// Internal entry points used by the server (dgs_api.cpp).  With a memory
+// pool, every device buffer of the call comes from it (stream-ordered on s)
+// and goes back to it before the call returns.
 dgs_status solve_internal(const int32_t *benefit, int32_t n, int32_t *assign_out, int64_t max_switches, bool dev,
-                          bool coop, hipStream_t s, dgs_result *res);
+                          bool coop, hipStream_t s, dgs_result *res, hipMemPool_t pool);
 dgs_status solve_batch_internal(int32_t count, const int32_t *const *benefits, const int32_t *ns,
                                 int32_t *const *outs, dgs_result *results, int64_t max_switches, int grid_cap,
-                                hipStream_t s);
+                                hipStream_t s, hipMemPool_t pool, BatchArena *arena);
 int device_cus();
 
 // Batched single-workgroup solver (dgs_batch.hip) for instances with n <= kBatchMaxN.
@@ -130,8 +140,9 @@ hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count,
 int batch_grid_limit(int block);
 
 // Parallel DGS (dgs_parallel.hip): one round of Check Conflicts over the
-// fresh bests in I.bk / I.bc (accepted partners into acc, stats[0] and [1]
-// advanced, stats[5] = accepted count) followed by the swaps.
+// fresh agent bests in I.bk / I.bc and job bests in I.bb (per owner agent),
+// the kept exchanges per agent into acc, then the swaps (stats[0] and [1]
+// advanced, stats[5] = kept count).
 int parallel_max_agents();
 hipError_t launch_parallel_round(const Instance &I, int32_t *acc, hipStream_t s);
 

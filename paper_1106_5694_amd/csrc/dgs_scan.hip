@@ -1,19 +1,28 @@
 // Difference evaluation of every agent (Section 3.2, Algorithm 2) on gfx950,
-// reading every entry of the working matrix once.
+// reading every entry of the benefit matrix once.
 //
 // With W[r][c] = a[r][tau(c)] and d[c] = W[c][c], the 2-exchange of agents
 // i and k gains g(i, k) = W[i][k] + W[k][i] - d[i] - d[k] = g(k, i).  The
 // agents are cut into blocks of kTile; the workgroup of block pair (I, K),
-// I <= K, loads tile W[I][K] and tile W[K][I] once and scores every pair
+// I <= K, loads the two tiles of the pair once and scores every pair
 // (i in I, k in K) for both agents: for agent i the candidate is
-// (g, job tau(k)), for agent k it is (g, job tau(i)).  Each workgroup writes
-// a top-2 (best, second) per agent and per partner block; k_scan_reduce
-// merges an agent's blocks into its best exchange and the second best
-// (the bound of the candidate list).  Ties: larger gain, then lower job.
+// (g, job tau(k)), for agent k it is (g, job tau(i)).  Ties: larger gain,
+// then lower job.
 //
-// g is symmetric in the two tiles, so the same scores come from V = W^T:
-// row x of V is row tau(x) of A^T (V[x][y] = a[y][tau(x)] = W[y][x]).  The
-// row-indirect variant reads the transpose through tau and needs no W.
+// g is symmetric in the two tiles, so it can be read from V = W^T, and row x
+// of V is row tau(x) of A^T (V[x][y] = a[y][tau(x)] = W[y][x]): the kernel
+// reads the transpose through tau, and no assignment-ordered matrix is ever
+// built (a switch changes tau, not the matrix).
+//
+// Two reductions of the scores:
+//   * lists (the steepest-ascent solve): a top-2 per agent and partner
+//     block; k_scan_reduce merges an agent's blocks into its best exchange,
+//     a candidate list and a bound for everything outside the list;
+//   * both sides (Parallel DGS and lazy DGS): per agent and partner block
+//     the best candidate keyed by job (the agent side, ADE) and the best
+//     keyed by partner agent (for agent c: the best agent to take c's job,
+//     the job side, JDE, lowest agent on ties); k_scan_best keeps the best
+//     of each.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -45,8 +54,7 @@ __device__ __forceinline__ void pair_of(long long p, int nb, int &I, int &K) {
 }
 
 struct ScanParams {
-    const int32_t *W;     // W, or A^T for the row-indirect variant
-    const int32_t *rows;  // row-indirect variant: tile row x is row rows[x] of the matrix
+    const int32_t *AT;    // A^T; tile row x is row tau[x] of it
     const int32_t *tau;
     const int32_t *d;
     u64 *part;  // [n][nb][2]
@@ -57,10 +65,10 @@ struct ScanParams {
 // One workgroup of BLOCK threads per tile pair: BLOCK / 64 threads per tile
 // row, each scoring 64 / (BLOCK / 64) partners on each side; interior pairs
 // (no bounds, no diagonal) take an unrolled path.
-// kByAgent: the candidate of agent i against partner k is keyed by k itself
-// instead of its job tau(k) -- the job side of the evaluation (the best agent
-// to take the job of agent i, lowest agent on ties).
-template <int BLOCK, bool kRows, bool kByAgent>
+// kBoth: slot 0 of a partial is the best candidate keyed by the partner's
+// job tau(k), slot 1 the best keyed by the partner agent k itself.
+// Otherwise the two slots are the top-2 by job.
+template <int BLOCK, bool kBoth>
 __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     constexpr int Q = BLOCK / 64;  // threads per tile row
     constexpr int E = kTile / Q;   // partners per thread
@@ -74,7 +82,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     const int i0 = I * kTile, k0 = K * kTile;
     const int t = threadIdx.x;
     const bool full = (n % 4 == 0) && i0 + kTile <= n && k0 + kTile <= n;
-    auto row = [&](int x) { return P.W + (int64_t)(kRows ? P.rows[x] : x) * n; };
+    auto row = [&](int x) { return P.AT + (int64_t)P.tau[x] * n; };
     if (full) {
         int4 va[LD], vb[LD];
 #pragma unroll
@@ -106,20 +114,23 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     }
     if (t < kTile) {
         dI[t] = i0 + t < n ? P.d[i0 + t] : 0;
-        jI[t] = i0 + t < n ? (kByAgent ? i0 + t : P.tau[i0 + t]) : 0;
+        jI[t] = i0 + t < n ? P.tau[i0 + t] : 0;
     } else if (t < 2 * kTile) {
         const int x = t - kTile;
         dK[x] = k0 + x < n ? P.d[k0 + x] : 0;
-        jK[x] = k0 + x < n ? (kByAgent ? k0 + x : P.tau[k0 + x]) : 0;
+        jK[x] = k0 + x < n ? P.tau[k0 + x] : 0;
     }
     __syncthreads();
 
-    // the row-indirect variant feeds best-only reductions: a top-1 suffices
-    auto push = [](u64 &b1, u64 &b2, u64 k) {
-        if constexpr (kRows)
-            b1 = umax64(b1, k);
-        else
-            top2_push(b1, b2, k);
+    // the both-sides reduction reads only bests: a top-1 per key kind
+    // (partner job x, partner agent y) suffices
+    auto push = [](u64 &b1, u64 &b2, int g, int x, int y) {
+        if constexpr (kBoth) {
+            b1 = umax64(b1, mk_key(g, x));
+            b2 = umax64(b2, mk_key(g, y));
+        } else {
+            top2_push(b1, b2, mk_key(g, x));
+        }
     };
     const int rt = t / Q, q = t % Q;
     u64 a1 = 0, a2 = 0, c1 = 0, c2 = 0;  // row rt of I against K; row rt of K against I
@@ -128,8 +139,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int c = q * E + e;
-            push(a1, a2, mk_key((tA[rt][c] + tB[c][rt]) - (di + dK[c]), jK[c]));
-            push(c1, c2, mk_key((tA[c][rt] + tB[rt][c]) - (dI[c] + dk), jI[c]));
+            push(a1, a2, (tA[rt][c] + tB[c][rt]) - (di + dK[c]), jK[c], k0 + c);
+            push(c1, c2, (tA[c][rt] + tB[rt][c]) - (dI[c] + dk), jI[c], i0 + c);
         }
     } else {
         if (i0 + rt < n) {
@@ -137,7 +148,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
             for (int e = 0; e < E; ++e) {
                 const int k = q * E + e;
                 if (k0 + k >= n || (I == K && k == rt)) continue;
-                push(a1, a2, mk_key((tA[rt][k] + tB[k][rt]) - (di + dK[k]), jK[k]));
+                push(a1, a2, (tA[rt][k] + tB[k][rt]) - (di + dK[k]), jK[k], k0 + k);
             }
         }
         if (I != K && k0 + rt < n) {
@@ -145,16 +156,18 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
             for (int e = 0; e < E; ++e) {
                 const int i = q * E + e;
                 if (i0 + i >= n) continue;
-                push(c1, c2, mk_key((tA[i][rt] + tB[rt][i]) - (dI[i] + dk), jI[i]));
+                push(c1, c2, (tA[i][rt] + tB[rt][i]) - (dI[i] + dk), jI[i], i0 + i);
             }
         }
     }
     // merge the Q threads of each row (adjacent lanes)
 #pragma unroll
     for (int m = 1; m < Q; m <<= 1) {
-        if constexpr (kRows) {
+        if constexpr (kBoth) {
             a1 = umax64(a1, shfl_xor64(a1, m));
+            a2 = umax64(a2, shfl_xor64(a2, m));
             c1 = umax64(c1, shfl_xor64(c1, m));
+            c2 = umax64(c2, shfl_xor64(c2, m));
         } else {
             top2_merge(a1, a2, shfl_xor64(a1, m), shfl_xor64(a2, m));
             top2_merge(c1, c2, shfl_xor64(c1, m), shfl_xor64(c2, m));
@@ -172,19 +185,29 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     }
 }
 
-// One wave per agent: the best of its nb block bests (no list, no bound).
+// One wave per agent: the best of its nb block bests of each key kind (no
+// list, no bound): by job into bk (with the partner sigma(job) into bc, if
+// given), by partner agent into ba.
 __global__ __launch_bounds__(256) void k_scan_best(const u64 *__restrict__ part, int n, int nb,
-                                                    const int32_t *__restrict__ sigma, u64 *bk, int32_t *bc) {
+                                                    const int32_t *__restrict__ sigma, u64 *bk, int32_t *bc,
+                                                    u64 *ba) {
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= n) return;
     const u64 *p = part + (size_t)r * nb * 2;
-    u64 m = 0;
-    for (int x = lane; x < nb; x += 64) m = umax64(m, p[2 * x]);
+    u64 m = 0, y = 0;
+    for (int x = lane; x < nb; x += 64) {
+        m = umax64(m, p[2 * x]);
+        y = umax64(y, p[2 * x + 1]);
+    }
 #pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) m = umax64(m, shfl_xor64(m, s));
+    for (int s = 32; s >= 1; s >>= 1) {
+        m = umax64(m, shfl_xor64(m, s));
+        y = umax64(y, shfl_xor64(y, s));
+    }
     if (lane == 0) {
         bk[r] = m;
+        ba[r] = y;
         if (bc) bc[r] = m ? sigma[key_index(m)] : -1;
     }
 }
@@ -263,26 +286,22 @@ size_t scan_pairs_scratch_bytes(int n) {
     return (size_t)n * nb * 2 * sizeof(u64);
 }
 
-hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s, bool by_agent, u64 *best,
-                                       int32_t *partner) {
+hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s, u64 *by_job,
+                                       int32_t *partner, u64 *by_agent) {
     const int nb = (I.n + kTile - 1) / kTile;
     const long long pairs = (long long)nb * (nb + 1) / 2;
-    ScanParams P{I.AT, I.tau, I.tau, I.d, (u64 *)scratch, I.n, nb};
-    if (by_agent)
-        hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true, true>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
-    else
-        hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s,
-                           P);
+    ScanParams P{I.AT, I.tau, I.d, (u64 *)scratch, I.n, nb};
+    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
     hipLaunchKernelGGL(k_scan_best, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
-                       nb, I.sigma, best ? best : I.bk, best ? partner : I.bc);
+                       nb, I.sigma, by_job, partner, by_agent);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s) {
     const int nb = (I.n + kTile - 1) / kTile;
     const long long pairs = (long long)nb * (nb + 1) / 2;
-    ScanParams P{I.W, nullptr, I.tau, I.d, (u64 *)scratch, I.n, nb};
-    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, false, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
+    ScanParams P{I.AT, I.tau, I.d, (u64 *)scratch, I.n, nb};
+    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
                        nb, I.sigma, I.bk, I.bb, I.bc, I.lists);
     return hipGetLastError();

@@ -14,6 +14,13 @@
 // while the workgroups of all running loops fit the device together, which
 // is what a cooperative launch would otherwise guarantee for a single one.
 // Every result is identical to dgs_solve on the same input.
+//
+// Device memory: every buffer of a request comes from a memory pool the
+// server owns (stream-ordered allocations on the worker's stream) and goes
+// back to it when the request completes; the pool keeps at most the budget
+// once its streams synchronize.  Admission keeps the footprints of the
+// requests on the device within the budget, so the memory the server holds
+// stays within the budget too (the library's own caches are not used).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -76,6 +83,8 @@ struct dgs_server {
     std::vector<std::thread> workers;
     std::vector<double> lat_us;
     int64_t submitted = 0, completed = 0;
+    hipMemPool_t pool = nullptr;  // every device buffer of the server's requests
+    dgs::BatchArena arena;        // host staging and events of the small-request worker
     Clock::time_point first_submit, last_finish;
     bool any_submit = false;
 };
@@ -137,7 +146,8 @@ void small_worker(dgs_server *s) {
             optr.push_back(outs[i].tau.data());
         }
         const dgs_status st = dgs::solve_batch_internal((int32_t)batch.size(), bens.data(), ns.data(),
-                                                        optr.data(), res.data(), -1, grid_cap, stream);
+                                                        optr.data(), res.data(), -1, grid_cap, stream, s->pool,
+                                                        &s->arena);
         const auto now = Clock::now();
         {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -195,7 +205,8 @@ void large_worker(dgs_server *s) {
         Done d;
         d.tau.resize((size_t)r.n);
         std::memset(&d.res, 0, sizeof d.res);
-        d.st = dgs::solve_internal(r.benefit, r.n, d.tau.data(), -1, false, /*coop=*/false, stream, &d.res);
+        d.st = dgs::solve_internal(r.benefit, r.n, d.tau.data(), -1, false, /*coop=*/false, stream, &d.res,
+                                   s->pool);
         d.finished = Clock::now();
         {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -227,7 +238,8 @@ extern "C" {
 uint64_t dgs_server_footprint(int32_t n) {
     const uint64_t nn = (uint64_t)n * (uint64_t)n;
     if (n <= dgs::kBatchMaxN) return 2 * 4 * nn + 32 * (uint64_t)n + 4096;  // copy + transpose
-    return 3 * 4 * nn + 2 * 16 * (uint64_t)n * (((uint64_t)n + 63) / 64) + 256 * (uint64_t)n + (1u << 20);
+    // device copy + transpose, evaluation partials, vectors and lists
+    return 2 * 4 * nn + 2 * 16 * (uint64_t)n * (((uint64_t)n + 63) / 64) + 256 * (uint64_t)n + (1u << 20);
 }
 
 dgs_status dgs_server_create(const dgs_server_config *cfg, dgs_server **out) {
@@ -237,6 +249,20 @@ dgs_status dgs_server_create(const dgs_server_config *cfg, dgs_server **out) {
     dgs_server *s = new dgs_server();
     s->cus = cus;
     s->cfg.hbm_budget_bytes = (cfg && cfg->hbm_budget_bytes) ? cfg->hbm_budget_bytes : (64ull << 30);
+    int device = 0;
+    bool ok = hipGetDevice(&device) == hipSuccess;
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    uint64_t keep = s->cfg.hbm_budget_bytes;  // freed blocks kept for reuse up to the budget
+    ok = ok && hipMemPoolCreate(&s->pool, &props) == hipSuccess;
+    ok = ok && hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess;
+    if (!ok) {
+        if (s->pool) (void)hipMemPoolDestroy(s->pool);
+        delete s;
+        return DGS_E_DEVICE;
+    }
     s->cfg.max_slots = (cfg && cfg->max_slots > 0) ? cfg->max_slots : 64;
     s->cfg.max_n = (cfg && cfg->max_n > 0) ? cfg->max_n : 16384;
     if (s->cfg.max_n > dgs::kSwitchExMaxN) s->cfg.max_n = dgs::kSwitchExMaxN;
@@ -326,7 +352,9 @@ void dgs_server_destroy(dgs_server *s) {
         s->stopping = true;
     }
     s->cv_work.notify_all();
-    for (auto &t : s->workers) t.join();
+    for (auto &t : s->workers) t.join();  // each worker synchronized and destroyed its stream
+    dgs::batch_arena_clear(s->arena);
+    (void)hipMemPoolDestroy(s->pool);
     delete s;
 }
 

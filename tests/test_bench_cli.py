@@ -26,7 +26,8 @@ def test_workloads_listed():
     assert r.returncode == 0
     for w in ("lowrank16384", "lowrank4096", "uniform256", "geom4096", "geom16384", "batched512", "serving"):
         assert w in r.stdout
-    for flag in ("--no-parallel", "--no-lazy", "--no-rect", "--no-batched", "--copy-calibration"):
+    for flag in ("--no-parallel", "--no-lazy", "--no-rect", "--no-batched", "--no-serving",
+                 "--serve-summary-seconds", "--sustained-rate", "--copy-calibration"):
         assert flag in r.stdout
 
 
@@ -35,8 +36,10 @@ def test_algorithmic_bytes_per_unit(n):
     nn = n * n
     assert bench.algorithmic_bytes("range", n, 0, 0) == 4 * nn
     assert bench.algorithmic_bytes("scan", n, 0, 0) == 4 * nn
-    assert bench.algorithmic_bytes("layout", n, 0, 0) == 16 * nn
-    assert bench.algorithmic_bytes("switch", n, 3, 5) == 16 * n * 3 + 8 * n * 5
+    assert bench.algorithmic_bytes("layout", n, 0, 0) == 8 * nn  # transpose: read + write
+    # per switch 16n B; the loop's own re-evaluations (8n B each) are reported apart
+    assert bench.algorithmic_bytes("switch", n, 3, 5) == 16 * n * 3
+    assert bench.reevaluation_bytes(n, 5) == 8 * n * 5
     with pytest.raises(KeyError):
         bench.algorithmic_bytes("nope", n, 0, 0)
 

@@ -54,6 +54,24 @@ def check(dgs, A, init=None, max_rounds=-1, what=""):
     return tau, res
 
 
+# Check Conflicts' job half (worked by hand in tests/test_oracle.py): from
+# tau = [2, 3, 0, 1, 4] (f = 50) round 1 keeps agent 0's exchange with agent 3
+# (+25) and job 4's exchange (agent 1 takes it, owner 4 takes job 3; +6), which
+# the agent half cannot keep (agent 4's best, tied with it, is towards agent 3).
+CC5_A = np.array([[8, 15, 1, 12, 3], [9, 13, 7, 7, 16], [18, 13, 18, 8, 0], [0, 4, 15, 4, 11],
+                  [2, 19, 7, 17, 20]], dtype=np.int32)
+
+
+def test_job_half_worked_example(dgs):
+    tau, res = dgs.solve(CC5_A, init=np.array([2, 3, 0, 1, 4], dtype=np.int32), parallel=True)
+    assert list(tau) == [1, 4, 0, 2, 3]
+    assert res["initial_benefit"] == 50 and res["total_benefit"] == 81
+    assert res["switches"] == 2 and res["rounds"] == 1
+    # one round bounded: the same state
+    tau1, res1 = dgs.solve(CC5_A, init=np.array([2, 3, 0, 1, 4], dtype=np.int32), max_switches=1, parallel=True)
+    assert list(tau1) == [1, 4, 0, 2, 3] and res1["switches"] == 2
+
+
 def test_worked_example_conflicts(dgs):
     tau, res = dgs.solve(PAR_A, init=np.arange(4, dtype=np.int32), parallel=True)
     assert list(tau) == [1, 0, 2, 3]
@@ -156,6 +174,22 @@ def test_lowrank16384_golden(dgs, seed):
 
 
 def test_ordered_walk_above_16384(dgs):
-    # n > 16384 takes the single-wave ordered walk of Check Conflicts
-    # instead of the in-LDS iteration; both must give the oracle's result
-    check(dgs, gen.uniform_matrix(16400, 0, 100000, 5), what="uniform n=16400")
+    # n > 16384 takes the single-wave ordered walk of Check Conflicts instead
+    # of the in-LDS iteration; its first rounds must give the oracle's result
+    # (ties: benefits from a small range)
+    check(dgs, gen.uniform_matrix(16400, 0, 1000, 5), max_rounds=2, what="uniform n=16400, two rounds")
+
+
+def test_lowrank20480_golden(dgs):
+    """The complete run above 16384 (walking Check Conflicts) against the
+    oracle's, stored by make_golden.py --full20480."""
+    gold = read_sections(os.path.join(HERE, "golden", "lowrank20480.txt"))["parallel_seed1"]
+    n = int(gold["n"])
+    say(f"parallel case lowrank{n} seed 1")
+    A = gen.lowrank_matrix(n, 1)
+    tau, res = dgs.solve(A, parallel=True)
+    h = hashlib.sha256(np.ascontiguousarray(tau, dtype="<i4").tobytes()).hexdigest()
+    assert res["initial_benefit"] == int(gold["greedy_f"])
+    assert res["total_benefit"] == int(gold["f"])
+    assert res["switches"] == int(gold["S"]) and res["rounds"] == int(gold["rounds"])
+    assert h == gold["tau_sha256"]

@@ -33,6 +33,8 @@ each point an average over several seeds, Section 4) with integer benefits:
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -104,15 +106,32 @@ def _row_chunks(n: int):
         yield r0, min(n, r0 + rows)
 
 
+def _fill_rows(n: int, fill) -> None:
+    """Run fill(r0, r1) over the row chunks of an n-row matrix on a few
+    threads (numpy releases the GIL in its array operations; the chunks
+    write disjoint rows, so the result does not depend on the order)."""
+    chunks = list(_row_chunks(n))
+    workers = min(16, os.cpu_count() or 1, len(chunks))
+    if workers <= 1:
+        for r0, r1 in chunks:
+            fill(r0, r1)
+        return
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda c: fill(*c), chunks))
+
+
 def uniform_matrix(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
     """n x n int32 matrix, entries iid uniform integers in [lo, hi)."""
     if n < 0 or hi <= lo:
         raise ValueError("need n >= 0 and hi > lo")
     out = np.empty((n, n), dtype=np.int32)
-    for r0, r1 in _row_chunks(n):
+
+    def fill(r0, r1):
         k = np.arange(r0 * n, r1 * n, dtype=np.uint64)
         vals = lo + to_int_below(draws(seed, S_UNIFORM, k), hi - lo)
         out[r0:r1] = vals.reshape(r1 - r0, n)
+
+    _fill_rows(n, fill)
     return out
 
 
@@ -129,13 +148,16 @@ def lowrank_matrix(n: int, seed: int, noise: int = 100, scale: float = 1000.0) -
     u, c = lowrank_factors(n, seed)
     su = scale * u
     out = np.empty((n, n), dtype=np.int32)
-    for r0, r1 in _row_chunks(n):
+
+    def fill(r0, r1):
         prod = su[r0:r1, None] * c[None, :]
         base = round_half_away(prod).astype(np.int64)
         if noise > 0:
             k = np.arange(r0 * n, r1 * n, dtype=np.uint64)
             base += to_int_below(draws(seed, S_NOISE, k), noise).reshape(r1 - r0, n)
         out[r0:r1] = base
+
+    _fill_rows(n, fill)
     return out
 
 
