@@ -283,6 +283,32 @@ dgs_status dgs_server_stats_get(dgs_server *s, dgs_server_stats *out);
 /* Waits for every queued request, then frees everything. */
 void dgs_server_destroy(dgs_server *s);
 
+/* ---- Solving without allocating ------------------------------------------
+ * For callers that cannot allocate device memory: code running while a HIP
+ * graph is being captured, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same computation and result as dgs_solve_ex with
+ * DGS_DEVICE_PTRS: benefit (n*n int32, row-major), assign_out (n int32) and
+ * opt->init_assign (if any, n int32) are device pointers on the calling
+ * thread's current device.  Every device buffer of the solve lives in one
+ * fixed array of DGS_NOALLOC_BYTES inside the library, one per GPU, held
+ * from the library's load until the process ends; hence n <=
+ * DGS_NOALLOC_MAX_N (larger n: DGS_E_INVAL).  The call allocates nothing: no
+ * hipMalloc, hipFree, pool or pinned host memory (results come back into a
+ * static host block).  Its first call on a device only looks up that GPU's
+ * array address and creates the timing events.  opt may be NULL;
+ * max_switches, init_assign, DGS_PROFILE and stream (NULL: the library's
+ * stream on the device the library first used, else the null stream) apply;
+ * DGS_PARALLEL and DGS_LAZY are rejected (DGS_E_INVAL).  The array keeps the
+ * last call's contents and every buffer is re-initialised by each call.
+ * Calls on one GPU share its array: the library serializes them with a
+ * lock, but work the caller enqueues itself that reads or overlaps a running
+ * call's buffers races with it.  Synchronous: returns once assign_out and
+ * res are written. */
+#define DGS_NOALLOC_MAX_N 4096
+#define DGS_NOALLOC_BYTES (72ull << 20) /* 4n^2 transpose + vectors at n = 4096 */
+dgs_status dgs_solve_noalloc(const int32_t *benefit, int32_t n, int32_t *assign_out,
+                             const dgs_options *opt, dgs_result *res);
+
 /* ---- Misc --------------------------------------------------------------- */
 
 const char *dgs_status_string(dgs_status st);

@@ -38,8 +38,9 @@ EXPORTS = (
     "dgs_server_wait", "dgs_server_stats_get", "dgs_server_destroy",
     "dgs_status_string", "dgs_last_error", "dgs_version", "dgs_release_cached",
     "dgs_batch_plan_create", "dgs_batch_plan_benefit", "dgs_batch_plan_assign", "dgs_batch_plan_run",
-    "dgs_batch_plan_config", "dgs_batch_plan_destroy",
+    "dgs_batch_plan_config", "dgs_batch_plan_destroy", "dgs_solve_noalloc",
 )
+NOALLOC_MAX_N = 4096
 
 
 class DGSError(RuntimeError):
@@ -102,6 +103,7 @@ def lib() -> ctypes.CDLL:
     L.dgs_solve.argtypes = [P, i32, P]
     L.dgs_solve_ex.argtypes = [P, i32, P, ctypes.POINTER(Options), ctypes.POINTER(Result)]
     L.dgs_solve_rect.argtypes = [P, i32, i32, P, ctypes.POINTER(Options), ctypes.POINTER(Result)]
+    L.dgs_solve_noalloc.argtypes = [P, i32, P, ctypes.POINTER(Options), ctypes.POINTER(Result)]
     L.dgs_solve_batched.argtypes = [i32, P, P, P, P, ctypes.POINTER(Options)]
     L.dgs_diff_eval.argtypes = [P, i32, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(Result)]
     L.dgs_server_footprint.argtypes = [i32]
@@ -127,7 +129,7 @@ def lib() -> ctypes.CDLL:
     L.dgs_last_error.restype = ctypes.c_char_p
     L.dgs_version.restype = ctypes.c_char_p
     L.dgs_release_cached.restype = None
-    for name in ("dgs_solve", "dgs_solve_ex", "dgs_solve_batched", "dgs_diff_eval", "dgs_server_create",
+    for name in ("dgs_solve", "dgs_solve_ex", "dgs_solve_noalloc", "dgs_solve_batched", "dgs_diff_eval", "dgs_server_create",
                  "dgs_server_submit", "dgs_server_poll", "dgs_server_wait", "dgs_server_stats_get",
                  "dgs_batch_plan_create", "dgs_batch_plan_run", "dgs_batch_plan_config"):
         getattr(L, name).restype = ctypes.c_int
@@ -211,6 +213,24 @@ def solve(A, init=None, max_switches: int = -1, profile: bool = False, parallel:
     st = L.dgs_solve_ex(Ah.ctypes.data, n, out.ctypes.data, ctypes.byref(opt), ctypes.byref(res))
     _check(st, "dgs_solve_ex")
     return out, res.as_dict()
+
+
+def solve_noalloc(A, out, init=None, max_switches: int = -1, profile: bool = False):
+    """Steepest-ascent DGS with no allocation in the library (dgs_solve_noalloc).
+
+    A: n x n contiguous int32 ROCm tensor (n <= NOALLOC_MAX_N); out: a
+    contiguous int32 ROCm tensor of n entries that receives tau; init:
+    optional start permutation (device tensor).  Runs on torch's current
+    stream.  Returns the result dict.
+    """
+    L = lib()
+    n = _square_n(A)
+    opt = Options(max_switches=int(max_switches), init_assign=init.data_ptr() if init is not None else None,
+                  flags=DGS_DEVICE_PTRS | (DGS_PROFILE if profile else 0), stream=_torch_stream_ptr())
+    res = Result()
+    st = L.dgs_solve_noalloc(A.data_ptr(), n, out.data_ptr(), ctypes.byref(opt), ctypes.byref(res))
+    _check(st, "dgs_solve_noalloc")
+    return res.as_dict()
 
 
 def solve_rect(A, init=None, max_switches: int = -1, profile: bool = False):

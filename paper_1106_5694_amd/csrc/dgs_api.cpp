@@ -306,6 +306,8 @@ struct Call {
     bool parallel = false;  // Parallel DGS rounds instead of the switching loop (max_switches = max rounds)
     bool lazy = false;      // lazy DGS passes (Algorithm 1 as printed) instead of the switching loop
     hipMemPool_t pool = nullptr;  // device buffers from this pool (stream-ordered) instead of the cache
+    Workspace *ws = nullptr;      // a workspace the caller holds (not taken from or returned to the cache)
+    HostRes *host = nullptr;      // host resources the caller holds (likewise)
     hipStream_t stream;
 };
 
@@ -373,27 +375,27 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
                   kLazyMaxN);
         return DGS_E_INVAL;
     }
-    if (c.assign_in) {
+    if (c.assign_in && !c.ws) {  // (a caller-held workspace comes with its own host-side check)
         dgs_status st = check_init(c.assign_in, n, c.dev, s);
         if (st != DGS_OK) return st;
     }
-    HostRes *h = nullptr;
-    dgs_status st = acquire_host(&h);
+    HostRes *h = c.host;
+    dgs_status st = h ? DGS_OK : acquire_host(&h);
     if (st != DGS_OK) return st;
-    Workspace *w = nullptr;
-    st = alloc_ws(n, !c.dev, c.pool, s, &w);
+    Workspace *w = c.ws;
+    st = w ? DGS_OK : alloc_ws(n, !c.dev, c.pool, s, &w);
     if (st != DGS_OK) {
-        release_host(h);
+        if (!c.host) release_host(h);
         return st;
     }
     struct Guard {
         Workspace *w;
         HostRes *h;
         ~Guard() {
-            release_ws(w);
-            release_host(h);
+            if (w) release_ws(w);
+            if (h) release_host(h);
         }
-    } guard{w, h};
+    } guard{c.ws ? nullptr : w, c.host ? nullptr : h};
 
     if (vec_layout(n).total > w->vec_bytes) {
         set_error("internal: workspace too small for n=%d", n);
@@ -776,8 +778,11 @@ dgs_status solve_batch_internal(int32_t count, const int32_t *const *benefits, c
 // workspaces, host resources, the batch arena) and its stream, while the HIP
 // runtime is still up.  Batch plans and servers belong to the caller, who
 // destroys them.
+void noalloc_release_events();
+
 void teardown_at_exit() {
     dgs_release_cached();
+    noalloc_release_events();
     if (g_ctx.stream) {
         (void)hipStreamSynchronize(g_ctx.stream);
         (void)hipStreamDestroy(g_ctx.stream);
@@ -785,6 +790,84 @@ void teardown_at_exit() {
     }
     g_ctx.init_status = DGS_E_DEVICE;
     g_ctx.init_error = "the library has been shut down (process exit)";
+}
+
+// ---- solving without allocating ------------------------------------------------------
+// dgs_solve_noalloc's device workspace is this fixed array: each GPU that
+// loads the library's code object holds its own copy until the process ends.
+// In host code the name `scratch` is only a host-side stand-in; the device
+// address of a GPU's copy comes from hipGetSymbolAddress, looked up once per
+// device with that device current, and only that address is ever handed to
+// kernels or copies.
+constexpr int32_t kNoAllocMaxN = DGS_NOALLOC_MAX_N;
+constexpr size_t kNoAllocBytes = (size_t)DGS_NOALLOC_BYTES;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct NoAllocDevice {
+    std::once_flag once;
+    dgs_status status = DGS_OK;
+    std::string error;
+    char *ptr = nullptr;   // device address of this GPU's `scratch`
+    HostRes host;          // timing events made at set-up; stats -> stats_buf
+    int64_t stats_buf[16] = {};
+    std::mutex mu;         // calls on one GPU run one at a time
+};
+
+NoAllocDevice g_noalloc[kMaxDevices];
+
+// Once per device, with that device current: the array's device address and
+// the call's timing events.  Nothing is allocated after this.
+dgs_status noalloc_setup(int device, NoAllocDevice **out) {
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("device %d outside the %d devices dgs_solve_noalloc supports", device, kMaxDevices);
+        return DGS_E_DEVICE;
+    }
+    NoAllocDevice &D = g_noalloc[device];
+    std::call_once(D.once, [&D] {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            D.status = DGS_E_DEVICE;
+            D.error = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+            return;
+        }
+        D.ptr = (char *)p;
+        bool ok = hipEventCreate(&D.host.ev0) == hipSuccess && hipEventCreate(&D.host.ev1) == hipSuccess;
+        for (auto &ev : D.host.ph) ok = ok && hipEventCreate(&ev) == hipSuccess;
+        if (!ok) {
+            D.status = DGS_E_DEVICE;
+            D.error = "hipEventCreate failed";
+            return;
+        }
+        D.host.stats = D.stats_buf;  // results are read back into this (pageable) block
+    });
+    if (D.status != DGS_OK) {
+        set_error("%s", D.error.c_str());
+        return D.status;
+    }
+    *out = &D;
+    return DGS_OK;
+}
+
+}  // namespace
+
+// At process exit (the arrays themselves go with the code object).
+void noalloc_release_events() {
+    for (NoAllocDevice &D : g_noalloc) {
+        if (!D.ptr) continue;
+        for (hipEvent_t *e : {&D.host.ev0, &D.host.ev1}) {
+            if (*e) (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
+        for (auto &e : D.host.ph) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    }
 }
 
 }  // namespace dgs
@@ -842,6 +925,65 @@ dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out, 
     c.parallel = opt && (opt->flags & DGS_PARALLEL);
     c.lazy = opt && (opt->flags & DGS_LAZY);
     c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
+    return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
+}
+
+dgs_status dgs_solve_noalloc(const int32_t *benefit, int32_t n, int32_t *assign_out, const dgs_options *opt,
+                             dgs_result *res) {
+    g_last_error.clear();
+    if (!benefit || !assign_out) {
+        set_error("NULL pointer argument");
+        return DGS_E_INVAL;
+    }
+    if (n < 1 || n > kNoAllocMaxN) {
+        set_error("n=%d outside [1, %d] (the fixed workspace of dgs_solve_noalloc)", n, kNoAllocMaxN);
+        return DGS_E_INVAL;
+    }
+    if (opt && (opt->flags & (DGS_PARALLEL | DGS_LAZY))) {
+        set_error("dgs_solve_noalloc runs the steepest-ascent mode only");
+        return DGS_E_INVAL;
+    }
+    dgs_status st = ensure_context();
+    if (st != DGS_OK) return st;
+    int device = 0;
+    DGS_HIP(hipGetDevice(&device));
+    NoAllocDevice *D = nullptr;
+    if ((st = noalloc_setup(device, &D)) != DGS_OK) return st;
+    std::lock_guard<std::mutex> lk(D->mu);
+    hipStream_t s = (opt && opt->stream) ? (hipStream_t)opt->stream
+                                         : (device == g_ctx.device ? g_ctx.stream : (hipStream_t)0);
+    const int32_t *init = opt ? opt->init_assign : nullptr;
+    if (init) {  // checked on the host without heap memory (n <= kNoAllocMaxN)
+        int32_t h[kNoAllocMaxN];
+        uint32_t seen[(kNoAllocMaxN + 31) / 32] = {};
+        DGS_HIP(hipMemcpyAsync(h, init, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        DGS_HIP(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t j = h[i];
+            if (j < 0 || j >= n || ((seen[j >> 5] >> (j & 31)) & 1u)) {
+                set_error("init_assign is not a permutation of 0..n-1");
+                return DGS_E_INVAL;
+            }
+            seen[j >> 5] |= 1u << (j & 31);
+        }
+    }
+    // the transpose first, then the vectors, all inside this GPU's array
+    const size_t mat = ((size_t)n * (size_t)n * 4 + 255) & ~(size_t)255;
+    Workspace w;
+    w.cap = n;
+    w.at = (int32_t *)D->ptr;
+    w.vec = D->ptr + mat;
+    w.vec_bytes = kNoAllocBytes - mat;
+    Call c;
+    c.benefit = benefit;
+    c.n = n;
+    c.assign_in = init;
+    c.max_switches = opt ? opt->max_switches : -1;
+    c.dev = true;
+    c.profile = opt && (opt->flags & DGS_PROFILE);
+    c.ws = &w;
+    c.host = &D->host;
+    c.stream = s;
     return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
 }
 
