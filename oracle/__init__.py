@@ -17,7 +17,10 @@ Contents:
     (Algorithm 4): rounds of the C agent and job scans and an index-order
     claim walk over agents, then jobs.
   * ``rect_dgs`` (below) -- steepest-ascent DGS for n agents and m >= n
-    jobs: swaps with other agents and moves to unassigned jobs, numpy.
+    jobs: swaps with other agents and moves to unassigned jobs, numpy;
+    ``rect_dgs_full`` the same in C (``orc_rect_dgs``) for larger sizes,
+    and ``global_greedy`` (``orc_global_greedy``) the global greedy start
+    (largest remaining entry first).
   * ``lazy_dgs`` (below) -- Algorithm 1 as printed (stale bests of agents
     and jobs, the branch rule, the improvement guard, repeated passes),
     with numpy row evaluations.
@@ -67,6 +70,11 @@ def lib():
                                    ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.orc_set_threads.restype = ctypes.c_int32
         L.orc_set_threads.argtypes = [ctypes.c_int32]
+        L.orc_global_greedy.restype = None
+        L.orc_global_greedy.argtypes = [i32p, ctypes.c_int32, ctypes.c_int32, i32p]
+        L.orc_rect_dgs.restype = ctypes.c_int64
+        L.orc_rect_dgs.argtypes = [i32p, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int64)]
         L.orc_hungarian.restype = ctypes.c_int64
         L.orc_hungarian.argtypes = [i32p, ctypes.c_int32, i32p]
         _lib = L
@@ -340,6 +348,31 @@ def rect_dgs(A, init=None, max_switches=-1):
         tau[i] = jj
         S += 1
     return dict(tau=tau.astype(np.int32), f=int(A[rows, tau].sum()), S=S)
+
+
+def global_greedy(A):
+    """n x m (n <= m): while an agent is free, the largest entry whose agent
+    and job are both free is taken (lowest agent, then lowest job, on ties).
+    C (sorted walk over all entries)."""
+    A = np.ascontiguousarray(A, dtype=np.int32)
+    n, m = A.shape
+    if n > m:
+        raise ValueError("need n <= m")
+    tau = np.empty(n, dtype=np.int32)
+    lib().orc_global_greedy(A, n, m, tau)
+    return tau
+
+
+def rect_dgs_full(A, init=None, max_switches=-1):
+    """rect_dgs in C: every agent re-evaluated over all m jobs after every
+    change (OpenMP over agents).  init: n distinct jobs (None: the greedy
+    start of rect_greedy).  Returns dict(tau, f, S)."""
+    A = np.ascontiguousarray(A, dtype=np.int32)
+    n, m = A.shape
+    tau = np.ascontiguousarray(rect_greedy(A) if init is None else init, dtype=np.int32).copy()
+    f = ctypes.c_int64(0)
+    S = lib().orc_rect_dgs(A, n, m, tau, int(max_switches), ctypes.byref(f))
+    return dict(tau=tau, f=int(f.value), S=int(S))
 
 
 def hungarian(A):

@@ -256,6 +256,27 @@ def rect_greedy(A):
     return tau
 
 
+def global_greedy(A):
+    """While an agent is free: among all entries whose agent and job are both
+    free, take a largest one (the lowest agent, then the lowest job, among
+    equal entries)."""
+    n, m = len(A), len(A[0])
+    tau = [-1] * n
+    job_free = [True] * m
+    for _ in range(n):
+        best = None
+        for i in range(n):
+            if tau[i] >= 0:
+                continue
+            for j in range(m):
+                if job_free[j] and (best is None or A[i][j] > best[0]):
+                    best = (A[i][j], i, j)
+        _, i, j = best
+        tau[i] = j
+        job_free[j] = False
+    return tau
+
+
 def rect_switch(i, j, tau):
     """Agent i takes job j; its owner, if any, takes tau(i); else the old job of
     i becomes unassigned."""

@@ -298,6 +298,107 @@ int64_t orc_dgs_incr(const int32_t *A, int32_t n, int32_t *tau, int64_t max_swit
     return S;
 }
 
+/* ---- rectangular instances: n agents, m >= n jobs (Section 1: n providers,
+ * m receivers).  Row stride m; sigma(j) = -1 for a job nobody holds, and
+ * exchange_gain's R6 branch (a move to that job) is live. ---------------- */
+
+/* One entry a_ij of the matrix, for the global greedy start. */
+typedef struct {
+    int32_t v, i, j;
+} orc_entry;
+
+/* Larger entry first; among equal entries the lower agent, then the lower
+ * job. */
+static int entry_before(const void *x, const void *y) {
+    const orc_entry *a = (const orc_entry *)x, *b = (const orc_entry *)y;
+    if (a->v != b->v) return a->v > b->v ? -1 : 1;
+    if (a->i != b->i) return a->i < b->i ? -1 : 1;
+    return a->j < b->j ? -1 : (a->j > b->j);
+}
+
+/*
+ * Global greedy start (the variant of Section 3.1's greedy start that looks
+ * at all benefits at once): while an agent is free, the largest entry a_ij
+ * whose agent i and job j are both free is taken (the lowest agent, then the
+ * lowest job, among equal entries).  Computed by putting every entry in
+ * that order once and walking it: the entry the definition takes next is
+ * always the first one left whose agent and job are both free, since an
+ * entry passed over has a taken agent or job, and taken stays taken.
+ * n <= m; tau receives n distinct jobs.
+ */
+void orc_global_greedy(const int32_t *A, int32_t n, int32_t m, int32_t *tau) {
+    const int64_t cnt = (int64_t)n * m;
+    orc_entry *e = (orc_entry *)malloc(sizeof(orc_entry) * (size_t)(cnt > 0 ? cnt : 1));
+    char *agent_taken = (char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    char *job_taken = (char *)calloc((size_t)(m > 0 ? m : 1), 1);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < m; ++j) {
+            e[i * m + j].v = A[i * m + j];
+            e[i * m + j].i = (int32_t)i;
+            e[i * m + j].j = (int32_t)j;
+        }
+    qsort(e, (size_t)cnt, sizeof(orc_entry), entry_before);
+    int32_t left = n;
+    for (int64_t x = 0; x < cnt && left > 0; ++x) {
+        if (agent_taken[e[x].i] || job_taken[e[x].j]) continue;
+        tau[e[x].i] = e[x].j;
+        agent_taken[e[x].i] = 1;
+        job_taken[e[x].j] = 1;
+        --left;
+    }
+    free(e);
+    free(agent_taken);
+    free(job_taken);
+}
+
+/* ADE of agent i over all m jobs j' != tau(i): exchanges with owned jobs,
+ * moves to free ones (R6); first strictly better wins (lowest job on ties). */
+static void ade_rect(const int32_t *A, int64_t m, const int32_t *tau, const int32_t *sigma,
+                     int64_t i, int64_t *g_out, int32_t *j_out) {
+    int64_t bg = ORC_NEG_INF;
+    int32_t bj = -1;
+    for (int64_t jp = 0; jp < m; ++jp) {
+        if (jp == tau[i]) continue;
+        int64_t g = exchange_gain(A, m, tau, sigma, i, jp);
+        if (g > bg) { bg = g; bj = (int32_t)jp; }
+    }
+    *g_out = bg;
+    *j_out = bj;
+}
+
+/*
+ * Steepest-ascent DGS on an n x m instance (n <= m) by definition: after
+ * every change every agent is re-evaluated from scratch over all m jobs;
+ * the best agent (largest gain, lowest agent on ties) is applied while its
+ * gain is > 0.  tau: n distinct jobs in [0, m), the start on entry and the
+ * result on exit.  Returns S; *f_out receives the final objective.
+ */
+int64_t orc_rect_dgs(const int32_t *A, int32_t n, int32_t m, int32_t *tau, int64_t max_switches,
+                     int64_t *f_out) {
+    int32_t *sigma = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int64_t *g = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *jb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t j = 0; j < m; ++j) sigma[j] = -1;
+    for (int32_t i = 0; i < n; ++i) sigma[tau[i]] = i;
+    int64_t f = 0, S = 0;
+    for (int64_t i = 0; i < n; ++i) f += at(A, m, i, tau[i]);
+    for (;;) {
+        if (max_switches >= 0 && S >= max_switches) break;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) ade_rect(A, m, tau, sigma, i, &g[i], &jb[i]);
+        int64_t i = pick(g, n);
+        if (i < 0) break;
+        apply_switch(tau, sigma, (int32_t)i, jb[i]);
+        f += g[i];
+        ++S;
+    }
+    *f_out = f;
+    free(sigma);
+    free(g);
+    free(jb);
+    return S;
+}
+
 /*
  * Exact LSAP optimum (maximisation), for the optimality gap.  Shortest
  * augmenting paths with dual potentials (the O(n^3) Hungarian method of

@@ -29,6 +29,11 @@ by steepest-ascent DGS -- the size whose switching launch gathers more than
 takes its walking variant above n = 16384.  ``--full20480 parallel`` (or
 steepest) rewrites only that section.
 
+With ``--rect`` it writes tests/golden/rect1000x16384.txt: rectangular
+steepest-ascent DGS (the C oracle's rect_dgs_full) on the first 1000 rows of
+the n = 16384 low-rank workload (1000 providers, 16384 receivers, seed 1),
+from the agent-order greedy start and from the global greedy start.
+
 With ``--lazy`` it writes tests/golden/lowrank16384_lazy.txt: the oracle's
 lazy DGS (Algorithm 1 as printed) from the greedy start of the n = 16384
 workload, seed 1.
@@ -55,6 +60,8 @@ OUT_PARALLEL = os.path.join(HERE, "lowrank16384_parallel.txt")
 OUT_LAZY = os.path.join(HERE, "lowrank16384_lazy.txt")
 OUT_GEOM = os.path.join(HERE, "geom16384.txt")
 OUT_FULL20480 = os.path.join(HERE, "lowrank20480.txt")
+OUT_RECT = os.path.join(HERE, "rect1000x16384.txt")
+RECT_N, RECT_M = 1000, 16384
 
 
 def replace_sections(path, header, sections):
@@ -209,6 +216,34 @@ def full20480(seed=1, modes=("steepest", "parallel")):
     replace_sections(OUT_FULL20480, header, sections)
 
 
+def rect(seed=1):
+    header = [f"# Oracle results of rectangular steepest-ascent DGS (swaps and moves to unassigned jobs)",
+              f"# on the first {RECT_N} rows of the n = {RECT_M} low-rank-plus-noise workload",
+              f"# (workloads.gen.lowrank_matrix({RECT_M}, seed, rows={RECT_N})): {RECT_N} agents, {RECT_M} jobs,",
+              "# run to the end from the agent-order greedy start (oracle.rect_dgs_full) and from",
+              "# the global greedy start (oracle.global_greedy); written by make_golden.py --rect.",
+              "# tau_sha256 as in lowrank16384.txt (the n agents' jobs)."]
+    t0 = time.time()
+    A = gen.lowrank_matrix(RECT_M, seed, rows=RECT_N)
+
+    def sha(t):
+        return hashlib.sha256(np.ascontiguousarray(t, dtype="<i4").tobytes()).hexdigest()
+
+    sections = {}
+    g = oracle.rect_greedy(A)
+    r = oracle.rect_dgs_full(A, init=g)
+    sections[f"greedy_seed{seed}"] = [f"start_f = {int(A[np.arange(RECT_N), g].sum())}", f"f = {r['f']}",
+                                      f"S = {r['S']}", f"tau_sha256 = {sha(r['tau'])}"]
+    print(f"rect greedy: S={r['S']} f={r['f']} ({time.time() - t0:.0f} s)", flush=True)
+    gg = oracle.global_greedy(A)
+    r = oracle.rect_dgs_full(A, init=gg)
+    sections[f"global_seed{seed}"] = [f"start_f = {int(A[np.arange(RECT_N), gg].sum())}",
+                                      f"start_sha256 = {sha(gg)}", f"f = {r['f']}", f"S = {r['S']}",
+                                      f"tau_sha256 = {sha(r['tau'])}"]
+    print(f"rect global greedy: S={r['S']} f={r['f']} ({time.time() - t0:.0f} s)", flush=True)
+    replace_sections(OUT_RECT, header, sections)
+
+
 if __name__ == "__main__":
     if sys.argv[1:2] == ["--prefix"]:
         prefix()
@@ -218,6 +253,8 @@ if __name__ == "__main__":
         lazy()
     elif sys.argv[1:2] == ["--geom"]:
         geom(modes=tuple(sys.argv[2:]) or ("steepest", "parallel", "lazy"))
+    elif sys.argv[1:2] == ["--rect"]:
+        rect()
     elif sys.argv[1:2] == ["--full20480"]:
         full20480(modes=tuple(sys.argv[2:]) or ("steepest", "parallel"))
     else:

@@ -505,3 +505,95 @@ def test_rect_square_is_steepest_ascent():
         A = gen.uniform_matrix(40, 0, 50 if seed % 2 else 4, 900 + seed)
         r, s = oracle.rect_dgs(A), oracle.dgs_full(A)
         assert list(r["tau"]) == list(s["tau"]) and r["f"] == s["f"] and r["S"] == s["S"]
+
+
+# Global greedy start (largest remaining entry first), worked by hand.
+# [[5, 9, 1], [2, 10, 3]]: the largest entry is 10 (agent 1, job 1); agent 0
+# then takes its best free job, 0 (5): tau = [0, 1], f = 15.  The
+# agent-order greedy gives tau = [1, 2] (9 + 3 = 12) instead.
+GG_A = [[5, 9, 1], [2, 10, 3]]
+# Ties: [[7, 0], [7, 5]] -- 7 twice in job 0: the lower agent 0 takes it,
+# then agent 1 takes job 1 (f = 12; agent 1 first would give f = 7).
+# [[7, 7], [0, 5]] -- 7 twice in agent 0: the lower job 0, then agent 1 takes
+# job 1 (f = 12; job 1 first would give f = 7).
+GG_TIES = [([[7, 0], [7, 5]], [0, 1]), ([[7, 7], [0, 5]], [0, 1])]
+
+
+def test_global_greedy_worked_examples():
+    assert dgs_ref.global_greedy(GG_A) == [0, 1]
+    assert list(oracle.global_greedy(np.array(GG_A))) == [0, 1]
+    assert dgs_ref.rect_greedy(GG_A) == [1, 2]
+    for A, tau in GG_TIES:
+        assert dgs_ref.global_greedy(A) == tau
+        assert list(oracle.global_greedy(np.array(A))) == tau
+
+
+@pytest.mark.parametrize("seed", range(80))
+def test_global_greedy_matches_definition(seed):
+    """The sorted walk (C) equals the repeated largest-entry definition on
+    small instances with many ties, negative values and n <= m."""
+    rng = np.random.default_rng(8100 + seed)
+    n = int(rng.integers(1, 7))
+    m = int(rng.integers(n, n + 5))
+    A = rng.integers(-5, 6 if seed % 3 else 2, (n, m)).astype(np.int32)
+    assert list(oracle.global_greedy(A)) == dgs_ref.global_greedy(A.tolist())
+
+
+@pytest.mark.parametrize("n,m,seed", [(50, 50, 1), (40, 300, 2), (200, 210, 3)])
+def test_global_greedy_rank_one_sorted_matching(n, m, seed):
+    """Closed form: a_ij = u_i * c_j with distinct positive u and c -- the
+    largest remaining entry always pairs the largest free u with the largest
+    free c, so agents in decreasing u get the jobs of the n largest c in
+    decreasing order."""
+    rng = np.random.default_rng(seed)
+    u = rng.permutation(np.arange(1, 4 * n + 1))[:n]
+    c = rng.permutation(np.arange(1, 4 * m + 1))[:m]
+    A = (u[:, None] * c[None, :]).astype(np.int32)
+    tau = oracle.global_greedy(A)
+    expect = np.empty(n, dtype=np.int64)
+    expect[np.argsort(-u)] = np.argsort(-c)[:n]
+    assert np.array_equal(tau, expect)
+
+
+def test_global_greedy_half_of_optimum():
+    """For nonnegative benefits the greedy matching is within a factor 2 of
+    the optimum (every optimal pair loses to a taken entry at least as
+    large on one of its two ends)."""
+    for seed in range(20):
+        A = gen.uniform_matrix(30, 0, 100, 300 + seed)
+        f = oracle.objective(A, oracle.global_greedy(A))
+        opt, _ = oracle.hungarian(A)
+        assert 2 * f >= opt
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_rect_dgs_c_matches_numpy(seed):
+    """orc_rect_dgs (C, full re-evaluation) == the numpy rect_dgs on random
+    instances (ties, negatives, given starts, the global greedy start,
+    prefixes)."""
+    rng = np.random.default_rng(9100 + seed)
+    n = int(rng.integers(1, 40))
+    m = int(rng.integers(n, n + 60))
+    A = rng.integers(-20, 20 if seed % 3 else 3, (n, m)).astype(np.int32)
+    init = None
+    if seed % 3 == 1:
+        init = [int(x) for x in rng.permutation(m)[:n]]
+    elif seed % 3 == 2:
+        init = [int(x) for x in oracle.global_greedy(A)]
+    ms = -1 if seed % 4 else int(rng.integers(0, 5))
+    a = oracle.rect_dgs_full(A, init=init, max_switches=ms)
+    b = oracle.rect_dgs(A, init=init, max_switches=ms)
+    assert np.array_equal(a["tau"], b["tau"]) and a["f"] == b["f"] and a["S"] == b["S"]
+
+
+def test_rect_from_global_greedy_worked_example():
+    """GG_A from the global greedy start (tau = [0, 1], f = 15): agent 0's
+    changes gain 1 - 5 (move to job 2) and 9 + 2 - 5 - 10 (swap); agent 1's
+    move to job 2 gains 3 - 10 and its swap is the same: nothing improves.  From
+    the agent-order start (tau = [1, 2], f = 12): agent 0's move to job 0
+    gains 5 - 9, the swap 1 + 10 - 9 - 3 = -1, agent 1's move to job 0
+    2 - 3: a local optimum at 12, below the global greedy start."""
+    r = oracle.rect_dgs_full(np.array(GG_A, dtype=np.int32), init=oracle.global_greedy(np.array(GG_A)))
+    assert list(r["tau"]) == [0, 1] and r["f"] == 15 and r["S"] == 0
+    s = oracle.rect_dgs_full(np.array(GG_A, dtype=np.int32))
+    assert list(s["tau"]) == [1, 2] and s["f"] == 12 and s["S"] == 0

@@ -100,17 +100,18 @@ def round_half_away(x: np.ndarray) -> np.ndarray:
     return np.where(x < 0, -r, r)
 
 
-def _row_chunks(n: int):
-    rows = max(1, _ROW_CHUNK_ELEMS // max(n, 1))
+def _row_chunks(n: int, cols: int = None):
+    rows = max(1, _ROW_CHUNK_ELEMS // max(n if cols is None else cols, 1))
     for r0 in range(0, n, rows):
         yield r0, min(n, r0 + rows)
 
 
-def _fill_rows(n: int, fill) -> None:
-    """Run fill(r0, r1) over the row chunks of an n-row matrix on a few
-    threads (numpy releases the GIL in its array operations; the chunks
-    write disjoint rows, so the result does not depend on the order)."""
-    chunks = list(_row_chunks(n))
+def _fill_rows(n: int, fill, cols: int = None) -> None:
+    """Run fill(r0, r1) over the row chunks of an n-row matrix (of `cols`
+    columns, default n) on a few threads (numpy releases the GIL in its
+    array operations; the chunks write disjoint rows, so the result does not
+    depend on the order)."""
+    chunks = list(_row_chunks(n, cols))
     workers = min(16, os.cpu_count() or 1, len(chunks))
     if workers <= 1:
         for r0, r1 in chunks:
@@ -143,11 +144,12 @@ def lowrank_factors(n: int, seed: int):
     return u, c
 
 
-def lowrank_matrix(n: int, seed: int, noise: int = 100, scale: float = 1000.0) -> np.ndarray:
-    """n x n int32: round((scale * u_i) * c_j) + noise_ij, noise uniform in [0, noise)."""
+def lowrank_matrix(n: int, seed: int, noise: int = 100, scale: float = 1000.0, rows: int = None) -> np.ndarray:
+    """n x n int32: round((scale * u_i) * c_j) + noise_ij, noise uniform in [0, noise).
+    rows: only the first `rows` rows (identical to slicing the full matrix)."""
     u, c = lowrank_factors(n, seed)
     su = scale * u
-    out = np.empty((n, n), dtype=np.int32)
+    out = np.empty((n if rows is None else rows, n), dtype=np.int32)
 
     def fill(r0, r1):
         prod = su[r0:r1, None] * c[None, :]
@@ -157,7 +159,7 @@ def lowrank_matrix(n: int, seed: int, noise: int = 100, scale: float = 1000.0) -
             base += to_int_below(draws(seed, S_NOISE, k), noise).reshape(r1 - r0, n)
         out[r0:r1] = base
 
-    _fill_rows(n, fill)
+    _fill_rows(out.shape[0], fill, n)
     return out
 
 
