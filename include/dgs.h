@@ -94,6 +94,18 @@ typedef enum dgs_status {
  * dgs_result.attempts = exchanges tried.  n <= 16384; not combinable with
  * DGS_PARALLEL. */
 #define DGS_LAZY 0x10u
+/* dgs_solve_ex and dgs_solve_rect: start from the global greedy assignment
+ * instead of the agent-order greedy one (Section 3.1 asks for a greedy start
+ * that takes the benefits into account; this is its variant that looks at
+ * all of them at once): while an agent is free, the largest entry a_ij over
+ * free agents and free jobs is taken (the lowest agent, then the lowest job,
+ * among equal entries).  Computed on the device in rounds of pairs that are
+ * the largest entry of both their row and their column among the free ones
+ * (all of them are taken by the one-at-a-time rule before anything that
+ * could block them); the rounds stop when every agent holds a job.  Ignored
+ * when init_assign is given; rejected by dgs_solve_batched and
+ * dgs_solve_noalloc (DGS_E_INVAL). */
+#define DGS_GLOBAL_GREEDY 0x20u
 
 /* dgs_result.phase_ms indices (filled only with DGS_PROFILE) */
 #define DGS_PHASE_RANGE 0  /* value-range check of the benefit matrix */
@@ -149,12 +161,15 @@ dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out,
  * a[i][j] - a[i][tau(i)]).  Each agent's best is the lowest job among its
  * largest gains; the best agent (lowest index on ties) is applied while its
  * gain is > 0.  The greedy start lets agents 0..n-1 take their best free job
- * in turn.  Implemented by padding to m x m with m - n agents of benefit 0
- * (a move is the 2-exchange with the padding agent that holds the free job),
- * so it takes m*m*4 bytes of device memory beyond the square path's needs.
- * opt may be NULL; init_assign (n distinct jobs), max_switches,
- * DGS_DEVICE_PTRS, DGS_PROFILE and stream apply; DGS_PARALLEL and DGS_LAZY
- * are rejected (DGS_E_INVAL), as are m < n and a non-injective init_assign. */
+ * in turn (DGS_GLOBAL_GREEDY: the global greedy start).  The solver treats
+ * each unassigned job as held by a virtual agent of benefit 0 (a move is the
+ * 2-exchange with it) whose row is never stored: device memory is the n*m
+ * matrix (copied in unless DGS_DEVICE_PTRS), its m*n transpose and O(m)
+ * vectors, and the evaluation reads the 2*n*m real entries.  m <=
+ * DGS_MAX_N_SWITCH.  opt may be NULL; init_assign (n distinct jobs),
+ * max_switches, DGS_DEVICE_PTRS, DGS_PROFILE, DGS_GLOBAL_GREEDY and stream
+ * apply; DGS_PARALLEL and DGS_LAZY are rejected (DGS_E_INVAL), as are m < n
+ * and a non-injective init_assign. */
 dgs_status dgs_solve_rect(const int32_t *benefit, int32_t n, int32_t m, int32_t *assign_out,
                           const dgs_options *opt, dgs_result *res);
 

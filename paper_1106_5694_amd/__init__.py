@@ -28,6 +28,7 @@ DGS_PROFILE = 0x2
 DGS_AUTOTUNE = 0x4
 DGS_PARALLEL = 0x8
 DGS_LAZY = 0x10
+DGS_GLOBAL_GREEDY = 0x20
 PHASES = ("range", "init", "layout", "scan", "switch")
 MAX_ABS_BENEFIT = (1 << 29) - 1
 
@@ -170,7 +171,7 @@ def _torch_stream_ptr():
 
 
 def solve(A, init=None, max_switches: int = -1, profile: bool = False, parallel: bool = False,
-          lazy: bool = False):
+          lazy: bool = False, global_greedy: bool = False):
     """Run DGS on one instance.
 
     A: n x n int32 benefit matrix (numpy / CPU tensor, or a ROCm tensor).
@@ -184,10 +185,13 @@ def solve(A, init=None, max_switches: int = -1, profile: bool = False, parallel:
     lazy: Algorithm 1 as printed (stale agent and job bests, the paper's
     branch rule and improvement guard); result["rounds"] = passes,
     result["attempts"] = exchanges tried.
+    global_greedy: start from the global greedy assignment (largest
+    remaining entry first) instead of the agent-order greedy one.
     """
     L = lib()
     n = _square_n(A)
-    extra = (DGS_PROFILE if profile else 0) | (DGS_PARALLEL if parallel else 0) | (DGS_LAZY if lazy else 0)
+    extra = ((DGS_PROFILE if profile else 0) | (DGS_PARALLEL if parallel else 0) | (DGS_LAZY if lazy else 0)
+             | (DGS_GLOBAL_GREEDY if global_greedy else 0))
     opt = Options(max_switches=int(max_switches), init_assign=None, flags=extra, stream=None)
     res = Result()
     if _is_device_tensor(A):
@@ -233,20 +237,21 @@ def solve_noalloc(A, out, init=None, max_switches: int = -1, profile: bool = Fal
     return res.as_dict()
 
 
-def solve_rect(A, init=None, max_switches: int = -1, profile: bool = False):
+def solve_rect(A, init=None, max_switches: int = -1, profile: bool = False, global_greedy: bool = False):
     """Steepest-ascent DGS on an n x m benefit matrix (n agents, m >= n jobs):
     swaps between agents and moves to unassigned jobs (dgs_solve_rect).
 
     A: n x m int32 (numpy / CPU tensor, or a ROCm tensor); init: optional n
-    distinct jobs.  Returns (tau, result) as solve() does.
+    distinct jobs; global_greedy: start from the global greedy assignment.
+    Returns (tau, result) as solve() does.
     """
     L = lib()
     shape = tuple(A.shape)
     if len(shape) != 2 or shape[0] > shape[1]:
         raise ValueError("benefit matrix must be n x m with n <= m")
     n, m = int(shape[0]), int(shape[1])
-    opt = Options(max_switches=int(max_switches), init_assign=None, flags=DGS_PROFILE if profile else 0,
-                  stream=None)
+    opt = Options(max_switches=int(max_switches), init_assign=None,
+                  flags=(DGS_PROFILE if profile else 0) | (DGS_GLOBAL_GREEDY if global_greedy else 0), stream=None)
     res = Result()
     if _is_device_tensor(A):
         import torch

@@ -88,7 +88,8 @@ namespace {
 // cache, then bounds the device memory it holds.
 
 struct Workspace {
-    int32_t cap = 0;
+    int32_t cap = 0;       // largest n of the vectors
+    size_t mat_bytes = 0;  // capacity of the transpose (and of the benefit copy)
     bool has_acopy = false;
     int32_t *acopy = nullptr;  // device copy of a host benefit matrix
     int32_t *at = nullptr;
@@ -154,7 +155,7 @@ void release_host(HostRes *h) {
 // 256-byte boundary; vec_layout() is the single source of the offsets used
 // both to size the allocation and to carve it.
 struct VecLayout {
-    size_t tau, sigma, d, bc, bk, bb, lists, stats, flags, words, greedy, scan, par, total;
+    size_t tau, sigma, d, bc, bk, bb, lists, stats, flags, words, greedy, glob, scan, par, total;
 };
 
 VecLayout vec_layout(int32_t n) {
@@ -177,6 +178,7 @@ VecLayout vec_layout(int32_t n) {
     const bool ex = n >= 2 && n <= kSwitchExMaxN;
     L.words = take(ex ? switch_v3_word_bytes(n) : 0);
     L.greedy = take(greedy_scratch_bytes(n));
+    L.glob = take(global_greedy_scratch_bytes(n, n));
     L.scan = take(scan_pairs_scratch_bytes(n));
     L.par = take((size_t)n * 4);
     L.total = off;
@@ -195,15 +197,18 @@ void free_ws(Workspace *w) {
     delete w;
 }
 
-// Device buffers for an instance of size n: from the cache (pool == NULL)
-// or from `pool`, ordered on `stream`.
-dgs_status alloc_ws(int32_t n, bool need_acopy, hipMemPool_t pool, hipStream_t stream, Workspace **out) {
+// Device buffers for an instance of n agents (nr of them real: matrices of
+// nr x n entries): from the cache (pool == NULL) or from `pool`, ordered on
+// `stream`.
+dgs_status alloc_ws(int32_t n, int32_t nr, bool need_acopy, hipMemPool_t pool, hipStream_t stream, Workspace **out) {
+    const size_t mat = (size_t)nr * (size_t)n * sizeof(int32_t);
     if (!pool) {
         std::lock_guard<std::mutex> lk(g_ws_mu);
         for (auto it = g_ws_free.lower_bound(n); it != g_ws_free.end(); ++it) {
             // do not hand a huge workspace to a tiny problem
             if (it->first > 2 * n + 1024) break;
             if (need_acopy && !it->second->has_acopy) continue;
+            if (it->second->mat_bytes < mat) continue;
             *out = it->second;
             g_ws_free.erase(it);
             return DGS_OK;
@@ -211,9 +216,9 @@ dgs_status alloc_ws(int32_t n, bool need_acopy, hipMemPool_t pool, hipStream_t s
     }
     Workspace *w = new Workspace();
     w->cap = n;
+    w->mat_bytes = mat;
     w->pool = pool;
     w->stream = stream;
-    const size_t mat = (size_t)n * (size_t)n * sizeof(int32_t);
     auto dev = [&](void **p, size_t bytes) {
         return (pool ? hipMallocFromPoolAsync(p, bytes, pool, stream) : hipMalloc(p, bytes)) == hipSuccess;
     };
@@ -244,9 +249,10 @@ void release_ws(Workspace *w) {
 }
 
 // Carve an Instance out of a workspace (n <= w->cap).
-Instance carve(Workspace *w, const int32_t *A, int32_t n) {
+Instance carve(Workspace *w, const int32_t *A, int32_t n, int32_t nr) {
     Instance I;
     I.n = n;
+    I.nr = nr;
     I.A = A;
     I.AT = w->at;
     const VecLayout L = vec_layout(n);
@@ -264,6 +270,7 @@ Instance carve(Workspace *w, const int32_t *A, int32_t n) {
     I.greedy = p + L.greedy;
     I.scan = p + L.scan;
     I.par = (int32_t *)(p + L.par);
+    I.glob = p + L.glob;
     return I;
 }
 
@@ -300,6 +307,9 @@ struct Call {
     int32_t n;
     const int32_t *assign_in;  // start (solve) or the assignment to evaluate
     int64_t max_switches;
+    int32_t nr = 0;            // real agents of a rectangular instance (benefit is nr x n); 0: square
+    bool init_host = false;    // assign_in is a host pointer even when dev is set
+    bool global_greedy = false;  // start from the global greedy (largest remaining entry first)
     bool dev;
     bool profile;
     bool coop = true;  // cooperative switching launch (else the caller owns co-residency)
@@ -327,7 +337,7 @@ dgs_status parallel_rounds(const Instance &I, HostRes *h, int64_t max_rounds, in
         ++rounds;
         if (max_rounds >= 0 && rounds >= max_rounds) break;
         // fresh d and evaluation; stats[6] takes the objective sum (f0 stays the start's)
-        DGS_HIP(launch_benefits(I.A, I.tau, I.n, I.d, I.stats + 6, s));
+        DGS_HIP(launch_benefits(I.A, I.tau, I.n, I.nr, I.d, I.stats + 6, s));
         DGS_HIP(launch_scan_best_transposed(I, I.scan, s, I.bk, I.bc, I.bb));
     }
     *rounds_out = rounds;
@@ -360,7 +370,12 @@ dgs_status lazy_passes(const Instance &I, HostRes *h, int64_t max_switches, int6
 dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *gain_out, int32_t *job_out,
                         dgs_result *res) {
     const int32_t n = c.n;
+    const int32_t nr = c.nr > 0 ? c.nr : n;  // real agents (rows of the benefit matrix)
     hipStream_t s = c.stream;
+    if (nr != n && (c.parallel || c.lazy || mode != Mode::Solve)) {
+        set_error("internal: rectangular instances run the steepest-ascent solve only");
+        return DGS_E_INVAL;
+    }
     if (c.parallel && n > parallel_max_agents()) {
         set_error("parallel mode supports n <= %d", parallel_max_agents());
         return DGS_E_INVAL;
@@ -375,15 +390,16 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
                   kLazyMaxN);
         return DGS_E_INVAL;
     }
+    const bool init_dev = c.dev && !c.init_host;
     if (c.assign_in && !c.ws) {  // (a caller-held workspace comes with its own host-side check)
-        dgs_status st = check_init(c.assign_in, n, c.dev, s);
+        dgs_status st = check_init(c.assign_in, n, init_dev, s);
         if (st != DGS_OK) return st;
     }
     HostRes *h = c.host;
     dgs_status st = h ? DGS_OK : acquire_host(&h);
     if (st != DGS_OK) return st;
     Workspace *w = c.ws;
-    st = w ? DGS_OK : alloc_ws(n, !c.dev, c.pool, s, &w);
+    st = w ? DGS_OK : alloc_ws(n, nr, !c.dev, c.pool, s, &w);
     if (st != DGS_OK) {
         if (!c.host) release_host(h);
         return st;
@@ -397,13 +413,13 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         }
     } guard{c.ws ? nullptr : w, c.host ? nullptr : h};
 
-    if (vec_layout(n).total > w->vec_bytes) {
+    const size_t mat = (size_t)nr * (size_t)n * sizeof(int32_t);
+    if (vec_layout(n).total > w->vec_bytes || mat > w->mat_bytes) {
         set_error("internal: workspace too small for n=%d", n);
         return DGS_E_NOMEM;
     }
     const int32_t *A = c.dev ? c.benefit : w->acopy;
-    Instance I = carve(w, A, n);
-    const size_t mat = (size_t)n * (size_t)n * sizeof(int32_t);
+    Instance I = carve(w, A, n, nr);
     if (!c.dev) DGS_HIP(hipMemcpyAsync(w->acopy, c.benefit, mat, hipMemcpyHostToDevice, s));
 
     DGS_HIP(hipEventRecord(h->ev0, s));
@@ -412,18 +428,24 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     DGS_HIP(launch_fill((int32_t *)I.stats, 16, 0, s));
     DGS_HIP(launch_fill(I.flags, 4, 0, s));
     DGS_HIP(mark(DGS_PHASE_RANGE));
-    DGS_HIP(launch_range_check(A, (int64_t)n * n, I.flags, s));
+    DGS_HIP(launch_range_check(A, (int64_t)nr * n, I.flags, s));
     DGS_HIP(mark(DGS_PHASE_INIT));
+    const bool gg = c.global_greedy && !c.assign_in;
     if (c.assign_in) {
         DGS_HIP(hipMemcpyAsync(I.tau, c.assign_in, (size_t)n * 4,
-                               c.dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+                               init_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         DGS_HIP(launch_invert_checked(I.tau, n, I.sigma, I.flags + 1, s));
+    } else if (gg) {
+        // the global greedy start reads columns too: the transpose comes first
+        DGS_HIP(launch_transpose(A, I.AT, nr, n, s));
+        int64_t gg_rounds = 0;
+        DGS_HIP(run_global_greedy(A, I.AT, nr, n, I.tau, I.sigma, I.glob, h->stats + 12, &gg_rounds, s));
     } else {
-        DGS_HIP(launch_greedy_rounds(A, n, I.tau, I.sigma, I.greedy, I.flags + 2, s));
+        DGS_HIP(launch_greedy_rounds(A, nr, n, I.tau, I.sigma, I.greedy, I.flags + 2, s));
     }
     DGS_HIP(mark(DGS_PHASE_LAYOUT));
-    DGS_HIP(launch_transpose(A, I.AT, n, s));
-    DGS_HIP(launch_benefits(A, I.tau, n, I.d, I.stats + 2, s));
+    if (!gg) DGS_HIP(launch_transpose(A, I.AT, nr, n, s));
+    DGS_HIP(launch_benefits(A, I.tau, n, nr, I.d, I.stats + 2, s));
     DGS_HIP(mark(DGS_PHASE_SCAN));
     if (c.parallel && mode == Mode::Solve)
         DGS_HIP(launch_scan_best_transposed(I, I.scan, s, I.bk, I.bc, I.bb));
@@ -473,8 +495,8 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         set_error("internal device check failed (code %d)", flags[2]);
         return DGS_E_DEVICE;
     }
-    if (mode == Mode::Solve) {
-        DGS_HIP(hipMemcpyAsync(assign_out, I.tau, (size_t)n * 4,
+    if (mode == Mode::Solve) {  // the real agents' jobs
+        DGS_HIP(hipMemcpyAsync(assign_out, I.tau, (size_t)nr * 4,
                                c.dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
         DGS_HIP(hipStreamSynchronize(s));
     }
@@ -924,6 +946,7 @@ dgs_status dgs_solve_ex(const int32_t *benefit, int32_t n, int32_t *assign_out, 
     c.profile = opt && (opt->flags & DGS_PROFILE);
     c.parallel = opt && (opt->flags & DGS_PARALLEL);
     c.lazy = opt && (opt->flags & DGS_LAZY);
+    c.global_greedy = opt && (opt->flags & DGS_GLOBAL_GREEDY);
     c.stream = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
     return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
 }
@@ -939,8 +962,8 @@ dgs_status dgs_solve_noalloc(const int32_t *benefit, int32_t n, int32_t *assign_
         set_error("n=%d outside [1, %d] (the fixed workspace of dgs_solve_noalloc)", n, kNoAllocMaxN);
         return DGS_E_INVAL;
     }
-    if (opt && (opt->flags & (DGS_PARALLEL | DGS_LAZY))) {
-        set_error("dgs_solve_noalloc runs the steepest-ascent mode only");
+    if (opt && (opt->flags & (DGS_PARALLEL | DGS_LAZY | DGS_GLOBAL_GREEDY))) {
+        set_error("dgs_solve_noalloc runs the steepest-ascent mode from the agent-order greedy start only");
         return DGS_E_INVAL;
     }
     dgs_status st = ensure_context();
@@ -971,6 +994,7 @@ dgs_status dgs_solve_noalloc(const int32_t *benefit, int32_t n, int32_t *assign_
     const size_t mat = ((size_t)n * (size_t)n * 4 + 255) & ~(size_t)255;
     Workspace w;
     w.cap = n;
+    w.mat_bytes = mat;
     w.at = (int32_t *)D->ptr;
     w.vec = D->ptr + mat;
     w.vec_bytes = kNoAllocBytes - mat;
@@ -1007,7 +1031,8 @@ dgs_status dgs_solve_rect(const int32_t *benefit, int32_t n, int32_t m, int32_t 
     if ((st = ensure_context()) != DGS_OK) return st;
     const bool dev = opt && (opt->flags & DGS_DEVICE_PTRS);
     hipStream_t s = (opt && opt->stream) ? (hipStream_t)opt->stream : g_ctx.stream;
-    // padded start: the caller's n jobs, then the unused jobs in increasing order
+    // a caller's start: its n jobs, then the unused jobs in increasing order
+    // for the virtual agents n..m-1 (host memory)
     std::vector<int32_t> init;
     if (opt && opt->init_assign) {
         init.resize((size_t)n);
@@ -1028,36 +1053,18 @@ dgs_status dgs_solve_rect(const int32_t *benefit, int32_t n, int32_t m, int32_t 
         for (int32_t j = 0; j < m; ++j)
             if (!used[(size_t)j]) init.push_back(j);
     }
-    const size_t rows = (size_t)n * (size_t)m * 4, mat = (size_t)m * (size_t)m * 4;
-    int32_t *P = nullptr, *pinit = nullptr, *pout = nullptr;
-    struct Bufs {
-        int32_t **p[3];
-        ~Bufs() {
-            for (auto q : p)
-                if (*q) (void)hipFree(*q);
-        }
-    } bufs{{&P, &pinit, &pout}};
-    if (hipMalloc((void **)&P, mat) != hipSuccess || hipMalloc((void **)&pout, (size_t)m * 4) != hipSuccess ||
-        (!init.empty() && hipMalloc((void **)&pinit, (size_t)m * 4) != hipSuccess)) {
-        set_error("device allocation of the padded %d x %d instance failed", m, m);
-        return DGS_E_NOMEM;
-    }
-    DGS_HIP(hipMemcpyAsync(P, benefit, rows, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
-    if (m > n) DGS_HIP(hipMemsetAsync((char *)P + rows, 0, mat - rows, s));
-    if (pinit) DGS_HIP(hipMemcpyAsync(pinit, init.data(), (size_t)m * 4, hipMemcpyHostToDevice, s));
     Call c;
-    c.benefit = P;
+    c.benefit = benefit;
     c.n = m;
-    c.assign_in = pinit;
+    c.nr = n;
+    c.assign_in = init.empty() ? nullptr : init.data();
+    c.init_host = true;
+    c.global_greedy = opt && (opt->flags & DGS_GLOBAL_GREEDY);
     c.max_switches = opt ? opt->max_switches : -1;
-    c.dev = true;
+    c.dev = dev;
     c.profile = opt && (opt->flags & DGS_PROFILE);
     c.stream = s;
-    st = run_instance(c, Mode::Solve, pout, nullptr, nullptr, res);
-    if (st != DGS_OK) return st;
-    DGS_HIP(hipMemcpyAsync(assign_out, pout, (size_t)n * 4, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
-    DGS_HIP(hipStreamSynchronize(s));
-    return DGS_OK;
+    return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
 }
 
 dgs_status dgs_diff_eval(const int32_t *benefit, int32_t n, const int32_t *assign, int64_t *gain_out,
@@ -1109,6 +1116,10 @@ dgs_status dgs_solve_batched(int32_t count, const int32_t *const *benefits, cons
     }
     if (opt && opt->init_assign) {
         set_error("init_assign is not supported for batches");
+        return DGS_E_INVAL;
+    }
+    if (opt && (opt->flags & (DGS_PARALLEL | DGS_LAZY | DGS_GLOBAL_GREEDY))) {
+        set_error("batches run the steepest-ascent mode from the agent-order greedy start only");
         return DGS_E_INVAL;
     }
     for (int32_t b = 0; b < count; ++b) {

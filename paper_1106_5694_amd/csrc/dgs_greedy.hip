@@ -146,7 +146,7 @@ struct TopkParams {
     const int32_t *A;
     const uint32_t *taken;  // bitmap of jobs taken before this round
     u64 *lists;             // [kRound][64]
-    int n;
+    int n;     // jobs (columns, the row stride of A)
     int row0;  // first agent of the round
 };
 
@@ -225,7 +225,7 @@ struct ResolveParams {
     int32_t *tau;
     int32_t *sigma;
     int32_t *err;
-    int n;
+    int n;  // jobs
     int row0;
     int rows;
 };
@@ -286,31 +286,198 @@ __global__ __launch_bounds__(256) void k_greedy_resolve(ResolveParams P) {
     }
 }
 
+// The virtual agents rows..n-1 of a rectangular instance take the jobs that
+// no real agent holds (sigma = -1), in increasing job order.  One workgroup:
+// each thread counts the free jobs of its stretch, an exclusive scan in LDS
+// gives its first virtual agent.
+constexpr int kFillBlock = 1024;
+
+__global__ __launch_bounds__(kFillBlock) void k_fill_virtual(int32_t *tau, int32_t *sigma, int rows, int n) {
+    __shared__ int cnt[kFillBlock];
+    const int t = threadIdx.x;
+    const int per = (n + kFillBlock - 1) / kFillBlock;
+    const int j0 = t * per, j1 = min(n, j0 + per);
+    int c = 0;
+    for (int j = j0; j < j1; ++j) c += sigma[j] < 0;
+    cnt[t] = c;
+    __syncthreads();
+    for (int off = 1; off < kFillBlock; off <<= 1) {  // inclusive scan (Hillis-Steele)
+        const int v = t >= off ? cnt[t - off] : 0;
+        __syncthreads();
+        cnt[t] += v;
+        __syncthreads();
+    }
+    int agent = rows + cnt[t] - c;
+    for (int j = j0; j < j1; ++j) {
+        if (sigma[j] >= 0) continue;
+        if (agent < n) {  // (exactly n - rows jobs are free)
+            tau[agent] = j;
+            sigma[j] = agent;
+        }
+        ++agent;
+    }
+}
+
+// ---- global greedy start ------------------------------------------------------------
+// While an agent is free, the largest entry a_ij over free agents i and free
+// jobs j is taken (the lowest agent, then the lowest job, among equal
+// entries: a strict order of the entries, the key (a_ij, -i, -j)).  Built
+// in rounds: a pair (i, j) whose entry is the largest of agent i's entries
+// over free jobs (the head of i) and of job j's entries over free agents (the
+// column best of j) is taken by the one-at-a-time rule before any other
+// entry of i or of j (every such entry left later is smaller), so all such
+// pairs of a round are taken together; every round takes at least the
+// largest remaining entry.  A head stays valid while its job is free and a
+// column best while its agent is free (the free sets only shrink), so only
+// invalidated ones are searched again.
+
+struct GGState {
+    const int32_t *A;   // rows x cols
+    const int32_t *AT;  // cols x rows
+    int32_t *tau;       // [rows] job of agent, -1 free
+    int32_t *sigma;     // [cols] agent of job, -1 free
+    int32_t *head;      // [rows] best free job of a free agent (-1 unknown)
+    int32_t *colbest;   // [cols] best free agent of a job (-1 unknown)
+    int32_t *want;      // [cols] last round in which some head pointed at the job
+    unsigned long long *count;  // agents matched so far
+    int rows, cols;
+};
+
+// One wave per free agent: its head (largest entry over free jobs, lowest job
+// on ties); marks the head's job as wanted in this round.
+__global__ __launch_bounds__(256) void k_gg_heads(GGState P, int round) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= P.rows || P.tau[i] >= 0) return;
+    int h = P.head[i];
+    if (h < 0 || P.sigma[h] >= 0) {
+        const int32_t *row = P.A + (int64_t)i * P.cols;
+        u64 best = 0;
+        int j = lane;
+        for (; j + 192 < P.cols; j += 256) {  // four requests in flight per lane
+            const int v0 = row[j], v1 = row[j + 64], v2 = row[j + 128], v3 = row[j + 192];
+            const int s0 = P.sigma[j], s1 = P.sigma[j + 64], s2 = P.sigma[j + 128], s3 = P.sigma[j + 192];
+            if (s0 < 0) best = umax64(best, mk_key(v0, j));
+            if (s1 < 0) best = umax64(best, mk_key(v1, j + 64));
+            if (s2 < 0) best = umax64(best, mk_key(v2, j + 128));
+            if (s3 < 0) best = umax64(best, mk_key(v3, j + 192));
+        }
+        for (; j < P.cols; j += 64)
+            if (P.sigma[j] < 0) best = umax64(best, mk_key(row[j], j));
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) best = umax64(best, shfl_xor64(best, m));
+        h = best ? key_index(best) : -1;  // rows <= cols: a free job always exists
+        if (lane == 0) P.head[i] = h;
+    }
+    if (lane == 0 && h >= 0) P.want[h] = round;
+}
+
+// One wave per wanted job: its column best (largest entry over free agents,
+// lowest agent on ties), searched again only when its agent was taken.
+__global__ __launch_bounds__(256) void k_gg_cols(GGState P, int round) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= P.cols || P.want[j] != round) return;
+    const int c = P.colbest[j];
+    if (c >= 0 && P.tau[c] < 0) return;
+    const int32_t *col = P.AT + (int64_t)j * P.rows;
+    u64 best = 0;
+    for (int i = lane; i < P.rows; i += 64)
+        if (P.tau[i] < 0) best = umax64(best, mk_key(col[i], i));
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) best = umax64(best, shfl_xor64(best, m));
+    if (lane == 0) P.colbest[j] = best ? key_index(best) : -1;
+}
+
+// A free agent whose head's column best is itself takes its head.
+__global__ __launch_bounds__(256) void k_gg_match(GGState P) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= P.rows || P.tau[i] >= 0) return;
+    const int h = P.head[i];
+    if (h >= 0 && P.colbest[h] == i) {
+        P.tau[i] = h;
+        P.sigma[h] = i;
+        atomicAdd(P.count, 1ull);
+    }
+}
+
 }  // namespace
+
+size_t global_greedy_scratch_bytes(int rows, int cols) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return al((size_t)rows * 4) + 2 * al((size_t)cols * 4) + 256;
+}
+
+hipError_t run_global_greedy(const int32_t *A, const int32_t *AT, int32_t rows, int32_t cols, int32_t *tau,
+                             int32_t *sigma, void *scratch, int64_t *host_count, int64_t *rounds_out,
+                             hipStream_t s) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    char *p = (char *)scratch;
+    GGState P;
+    P.A = A;
+    P.AT = AT;
+    P.tau = tau;
+    P.sigma = sigma;
+    P.head = (int32_t *)p;
+    P.colbest = (int32_t *)(p + al((size_t)rows * 4));
+    P.want = (int32_t *)(p + al((size_t)rows * 4) + al((size_t)cols * 4));
+    P.count = (unsigned long long *)(p + al((size_t)rows * 4) + 2 * al((size_t)cols * 4));
+    P.rows = rows;
+    P.cols = cols;
+    hipError_t e;
+    if ((e = launch_fill(tau, rows, -1, s)) != hipSuccess || (e = launch_fill(sigma, cols, -1, s)) != hipSuccess ||
+        (e = launch_fill(P.head, rows, -1, s)) != hipSuccess ||
+        (e = launch_fill(P.colbest, cols, -1, s)) != hipSuccess ||
+        (e = launch_fill(P.want, cols, -1, s)) != hipSuccess || (e = launch_fill((int32_t *)P.count, 2, 0, s)) != hipSuccess)
+        return e;
+    const unsigned gh = (unsigned)((rows + 3) / 4), gc = (unsigned)((cols + 3) / 4), gm = (unsigned)((rows + 255) / 256);
+    constexpr int kPerCheck = 8;  // rounds between reads of the matched count (extra rounds are empty)
+    int round = 0;
+    for (;;) {
+        for (int k = 0; k < kPerCheck; ++k, ++round) {
+            hipLaunchKernelGGL(k_gg_heads, dim3(gh), dim3(256), 0, s, P, round);
+            hipLaunchKernelGGL(k_gg_cols, dim3(gc), dim3(256), 0, s, P, round);
+            hipLaunchKernelGGL(k_gg_match, dim3(gm), dim3(256), 0, s, P);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(host_count, P.count, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        if (*host_count >= rows) break;
+        if (round > rows + kPerCheck) return hipErrorUnknown;  // every round takes a pair: cannot happen
+    }
+    *rounds_out = round;
+    return launch_fill_virtual(tau, sigma, rows, cols, s);
+}
+
+hipError_t launch_fill_virtual(int32_t *tau, int32_t *sigma, int32_t rows, int32_t n, hipStream_t s) {
+    if (rows >= n) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_virtual, dim3(1), dim3(kFillBlock), 0, s, tau, sigma, rows, n);
+    return hipGetLastError();
+}
 
 size_t greedy_scratch_bytes(int n) {
     return (size_t)kRound * 64 * sizeof(u64) + (((size_t)n + 31) / 32) * 4 + 256;
 }
 
-hipError_t launch_greedy_rounds(const int32_t *A, int32_t n, int32_t *tau, int32_t *sigma, void *scratch,
-                                int32_t *err, hipStream_t s) {
+hipError_t launch_greedy_rounds(const int32_t *A, int32_t rows, int32_t n, int32_t *tau, int32_t *sigma,
+                                void *scratch, int32_t *err, hipStream_t s) {
     u64 *lists = (u64 *)scratch;
     uint32_t *taken = (uint32_t *)((char *)scratch + (size_t)kRound * 64 * sizeof(u64));
     const int words = (n + 31) / 32;
     hipError_t e = launch_fill((int32_t *)taken, words, 0, s);
     if (e != hipSuccess) return e;
+    if (rows < n && (e = launch_fill(sigma, n, -1, s)) != hipSuccess) return e;
     const size_t rshm = (size_t)kRound * 64 * sizeof(u64) + (size_t)words * 4;
     e = hipFuncSetAttribute((const void *)k_greedy_resolve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rshm);
     if (e != hipSuccess) return e;
-    for (int row0 = 0; row0 < n; row0 += kRound) {
-        const int rows = n - row0 < kRound ? n - row0 : kRound;
+    for (int row0 = 0; row0 < rows; row0 += kRound) {
+        const int cnt = rows - row0 < kRound ? rows - row0 : kRound;
         TopkParams T{A, taken, lists, n, row0};
-        hipLaunchKernelGGL(k_greedy_topk, dim3((unsigned)rows), dim3(kTopkBlock), 0, s, T);
-        ResolveParams R{lists, taken, tau, sigma, err, n, row0, rows};
-        const size_t shm = (size_t)rows * 64 * sizeof(u64) + (size_t)words * 4;
+        hipLaunchKernelGGL(k_greedy_topk, dim3((unsigned)cnt), dim3(kTopkBlock), 0, s, T);
+        ResolveParams R{lists, taken, tau, sigma, err, n, row0, cnt};
+        const size_t shm = (size_t)cnt * 64 * sizeof(u64) + (size_t)words * 4;
         hipLaunchKernelGGL(k_greedy_resolve, dim3(1), dim3(256), shm, s, R);
     }
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_fill_virtual(tau, sigma, rows, n, s);
 }
 
 }  // namespace dgs

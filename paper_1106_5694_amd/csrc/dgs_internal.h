@@ -29,8 +29,15 @@ typedef unsigned long long u64;
 // Length of the candidate lists the full evaluation hands to the switching loop.
 constexpr int kScanListLen = 8;
 
+// Rectangular instances (nr agents, n >= nr jobs) run as n agents: agents
+// nr..n-1 are virtual agents of benefit 0 for every job, each holding one
+// job nobody really holds, so an exchange with one of them is a real
+// agent's move to an unassigned job.  Their rows are never stored: A is
+// nr x n (row stride n) and AT is n x nr (row stride nr); every read of a
+// virtual agent's benefit is 0.  Square instances have nr = n.
 struct Instance {
     int32_t n = 0;
+    int32_t nr = 0;  // real agents (rows of A); n for a square instance
     const int32_t *A = nullptr;
     int32_t *AT = nullptr;
     int32_t *tau = nullptr;
@@ -45,6 +52,7 @@ struct Instance {
     int32_t *flags = nullptr;    // [0] range error, [1] permutation error, [2] wait timed out
     void *words = nullptr;       // exchange words of the switching loop
     void *greedy = nullptr;      // scratch of the greedy start
+    void *glob = nullptr;        // scratch of the global greedy start
     void *scan = nullptr;        // scratch of the difference evaluation (per-block top-2)
     u64 *lists = nullptr;        // [n][kScanListLen] initial candidate lists (keys, 0 = empty)
     int32_t *par = nullptr;      // [n] Parallel DGS: partner of each accepted agent, else -1
@@ -67,15 +75,31 @@ dgs_status ensure_context();            // device, stream and switch-loop grid, 
 hipError_t launch_range_check(const int32_t *A, int64_t count, int32_t *flag, hipStream_t s);
 // Greedy start in rounds (dgs_greedy.hip); scratch of greedy_scratch_bytes(n).
 size_t greedy_scratch_bytes(int n);
-hipError_t launch_greedy_rounds(const int32_t *A, int32_t n, int32_t *tau, int32_t *sigma, void *scratch,
-                                int32_t *err, hipStream_t s);
+// rows agents (0..rows-1) over cols jobs; agents rows..cols-1 then take the
+// jobs left free in increasing order.
+hipError_t launch_greedy_rounds(const int32_t *A, int32_t rows, int32_t cols, int32_t *tau, int32_t *sigma,
+                                void *scratch, int32_t *err, hipStream_t s);
+// Virtual agents rows..n-1 take the jobs with sigma = -1 in increasing order.
+hipError_t launch_fill_virtual(int32_t *tau, int32_t *sigma, int32_t rows, int32_t n, hipStream_t s);
+// Global greedy start (largest remaining entry first, lowest agent, then
+// lowest job, on ties) of rows agents over cols jobs, by rounds of locally
+// dominant pairs; AT is the cols x rows transpose; scratch of
+// global_greedy_scratch_bytes(rows, cols); the host reads the matched count
+// every few rounds into *host_count (pinned).  Agents rows..cols-1 then take
+// the jobs left free in increasing order.
+size_t global_greedy_scratch_bytes(int rows, int cols);
+hipError_t run_global_greedy(const int32_t *A, const int32_t *AT, int32_t rows, int32_t cols, int32_t *tau,
+                             int32_t *sigma, void *scratch, int64_t *host_count, int64_t *rounds_out,
+                             hipStream_t s);
 // p[0..n) = v (a kernel, so that it can sit in a captured graph)
 hipError_t launch_fill(int32_t *p, int32_t n, int32_t v, hipStream_t s);
 hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, int32_t *flag,
                                  hipStream_t s);
-hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t n, hipStream_t s);
-// d[r] = a[r][tau(r)] and the objective sum.
-hipError_t launch_benefits(const int32_t *A, const int32_t *tau, int32_t n, int32_t *d, int64_t *f, hipStream_t s);
+// AT (cols x rows) = transpose of A (rows x cols).
+hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t rows, int32_t cols, hipStream_t s);
+// d[r] = a[r][tau(r)] (0 for virtual agents r >= nr) and the objective sum.
+hipError_t launch_benefits(const int32_t *A, const int32_t *tau, int32_t n, int32_t nr, int32_t *d, int64_t *f,
+                           hipStream_t s);
 // Symmetric tile-pair difference evaluation from A^T through tau
 // (dgs_scan.hip): each agent's best exchange into I.bk / I.bc, its candidate
 // list into I.lists and the list's bound into I.bb.

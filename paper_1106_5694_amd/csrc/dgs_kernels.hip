@@ -62,30 +62,31 @@ __global__ void k_invert_checked(const int32_t *__restrict__ tau, int n, int32_t
 
 // ---- layout build ---------------------------------------------------------------
 
+// AT (cols x rows) = A^T for A (rows x cols): 64 x 64 tiles through LDS.
 __global__ __launch_bounds__(256) void k_transpose(const int32_t *__restrict__ A, int32_t *__restrict__ AT,
-                                                     int n) {
+                                                     int rows, int cols) {
     __shared__ int32_t tile[64][65];
-    const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
+    const int bx = blockIdx.x * 64, by = blockIdx.y * 64;  // column and row offsets in A
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int r = ty; r < 64; r += 4) {
         int row = by + r, col = bx + tx;
-        if (row < n && col < n) tile[r][tx] = A[(int64_t)row * n + col];
+        if (row < rows && col < cols) tile[r][tx] = A[(int64_t)row * cols + col];
     }
     __syncthreads();
     for (int r = ty; r < 64; r += 4) {
         int row = bx + r, col = by + tx;
-        if (row < n && col < n) AT[(int64_t)row * n + col] = tile[tx][r];
+        if (row < cols && col < rows) AT[(int64_t)row * rows + col] = tile[tx][r];
     }
 }
 
-// d[r] = a[r][tau(r)] and f0 = sum of d.
+// d[r] = a[r][tau(r)] (0 for the virtual agents r >= nr) and f0 = sum of d.
 __global__ __launch_bounds__(256) void k_benefits(const int32_t *__restrict__ A, const int32_t *__restrict__ tau,
-                                                    int n, int32_t *d, unsigned long long *f0) {
+                                                    int n, int nr, int32_t *d, unsigned long long *f0) {
     __shared__ long long part[4];
     const int r = blockIdx.x * 256 + threadIdx.x;
     long long v = 0;
     if (r < n) {
-        const int x = A[(int64_t)r * n + tau[r]];
+        const int x = r < nr ? A[(int64_t)r * n + tau[r]] : 0;
         d[r] = x;
         v = x;
     }
@@ -129,14 +130,15 @@ hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, 
     return hipGetLastError();
 }
 
-hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t n, hipStream_t s) {
-    unsigned t = (unsigned)((n + 63) / 64);
-    hipLaunchKernelGGL(k_transpose, dim3(t, t), dim3(256), 0, s, A, AT, n);
+hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t rows, int32_t cols, hipStream_t s) {
+    const unsigned tc = (unsigned)((cols + 63) / 64), tr = (unsigned)((rows + 63) / 64);
+    hipLaunchKernelGGL(k_transpose, dim3(tc, tr), dim3(256), 0, s, A, AT, rows, cols);
     return hipGetLastError();
 }
 
-hipError_t launch_benefits(const int32_t *A, const int32_t *tau, int32_t n, int32_t *d, int64_t *f, hipStream_t s) {
-    hipLaunchKernelGGL(k_benefits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, tau, n, d,
+hipError_t launch_benefits(const int32_t *A, const int32_t *tau, int32_t n, int32_t nr, int32_t *d, int64_t *f,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_benefits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, tau, n, nr, d,
                        (unsigned long long *)f);
     return hipGetLastError();
 }

@@ -54,11 +54,12 @@ __device__ __forceinline__ void pair_of(long long p, int nb, int &I, int &K) {
 }
 
 struct ScanParams {
-    const int32_t *AT;    // A^T; tile row x is row tau[x] of it
+    const int32_t *AT;    // A^T (n x nr); tile row x is row tau[x] of it
     const int32_t *tau;
     const int32_t *d;
-    u64 *part;  // [n][nb][2]
-    int n;
+    u64 *part;  // [nr][nb][2]
+    int n;      // agents (with the virtual ones of a rectangular instance)
+    int nr;     // real agents: entries of virtual agents y >= nr are 0, and only real agents get results
     int nb;
 };
 
@@ -78,11 +79,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     __shared__ int32_t dI[kTile], dK[kTile], jI[kTile], jK[kTile];
     int I, K;
     pair_of((long long)blockIdx.x, P.nb, I, K);
-    const int n = P.n;
+    const int n = P.n, nr = P.nr;
     const int i0 = I * kTile, k0 = K * kTile;
     const int t = threadIdx.x;
-    const bool full = (n % 4 == 0) && i0 + kTile <= n && k0 + kTile <= n;
-    auto row = [&](int x) { return P.AT + (int64_t)P.tau[x] * n; };
+    const bool full = (nr % 4 == 0) && i0 + kTile <= nr && k0 + kTile <= nr;
+    auto row = [&](int x) { return P.AT + (int64_t)P.tau[x] * nr; };
     if (full) {
         int4 va[LD], vb[LD];
 #pragma unroll
@@ -108,8 +109,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
     } else {
         for (int e = t; e < kTile * kTile; e += BLOCK) {
             const int r = e >> 6, c = e & 63;
-            tA[r][c] = (i0 + r < n && k0 + c < n) ? row(i0 + r)[k0 + c] : 0;
-            tB[r][c] = (k0 + r < n && i0 + c < n) ? row(k0 + r)[i0 + c] : 0;
+            tA[r][c] = (i0 + r < n && k0 + c < nr) ? row(i0 + r)[k0 + c] : 0;
+            tB[r][c] = (k0 + r < n && i0 + c < nr) ? row(k0 + r)[i0 + c] : 0;
         }
     }
     if (t < kTile) {
@@ -173,12 +174,12 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pairs_b(ScanParams P) {
             top2_merge(c1, c2, shfl_xor64(c1, m), shfl_xor64(c2, m));
         }
     }
-    if (q == 0 && i0 + rt < n) {
+    if (q == 0 && i0 + rt < nr) {
         u64 *o = P.part + ((size_t)(i0 + rt) * P.nb + K) * 2;
         o[0] = a1;
         o[1] = a2;
     }
-    if (q == 0 && I != K && k0 + rt < n) {
+    if (q == 0 && I != K && k0 + rt < nr) {
         u64 *o = P.part + ((size_t)(k0 + rt) * P.nb + I) * 2;
         o[0] = c1;
         o[1] = c2;
@@ -286,23 +287,30 @@ size_t scan_pairs_scratch_bytes(int n) {
     return (size_t)n * nb * 2 * sizeof(u64);
 }
 
+// Tile pairs (I, K), I <= K, with a real agent in block I: the first ones of
+// the row-major triangular order (pairs of two virtual blocks score nothing
+// a real agent needs).
+static long long scan_pairs_count(int nb, int nbr) {
+    return (long long)nbr * nb - (long long)nbr * (nbr - 1) / 2;
+}
+
 hipError_t launch_scan_best_transposed(const Instance &I, void *scratch, hipStream_t s, u64 *by_job,
                                        int32_t *partner, u64 *by_agent) {
-    const int nb = (I.n + kTile - 1) / kTile;
-    const long long pairs = (long long)nb * (nb + 1) / 2;
-    ScanParams P{I.AT, I.tau, I.d, (u64 *)scratch, I.n, nb};
-    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
-    hipLaunchKernelGGL(k_scan_best, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
+    const int nb = (I.n + kTile - 1) / kTile, nbr = (I.nr + kTile - 1) / kTile;
+    ScanParams P{I.AT, I.tau, I.d, (u64 *)scratch, I.n, I.nr, nb};
+    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, true>), dim3((unsigned)scan_pairs_count(nb, nbr)),
+                       dim3(kScanBlock), 0, s, P);
+    hipLaunchKernelGGL(k_scan_best, dim3((unsigned)((I.nr + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.nr,
                        nb, I.sigma, by_job, partner, by_agent);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_pairs(const Instance &I, void *scratch, hipStream_t s) {
-    const int nb = (I.n + kTile - 1) / kTile;
-    const long long pairs = (long long)nb * (nb + 1) / 2;
-    ScanParams P{I.AT, I.tau, I.d, (u64 *)scratch, I.n, nb};
-    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, false>), dim3((unsigned)pairs), dim3(kScanBlock), 0, s, P);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)((I.n + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.n,
+    const int nb = (I.n + kTile - 1) / kTile, nbr = (I.nr + kTile - 1) / kTile;
+    ScanParams P{I.AT, I.tau, I.d, (u64 *)scratch, I.n, I.nr, nb};
+    hipLaunchKernelGGL((k_scan_pairs_b<kScanBlock, false>), dim3((unsigned)scan_pairs_count(nb, nbr)),
+                       dim3(kScanBlock), 0, s, P);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)((I.nr + 3) / 4)), dim3(256), 0, s, (const u64 *)scratch, I.nr,
                        nb, I.sigma, I.bk, I.bb, I.bc, I.lists);
     return hipGetLastError();
 }

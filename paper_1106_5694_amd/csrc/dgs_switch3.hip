@@ -205,8 +205,8 @@ __device__ __forceinline__ void list_drop_jobs(u64 (&L)[kM], int j1, int j2) {
 __device__ __forceinline__ int lanes_below(u64 bal, int lane) { return __popcll(bal & ((1ull << lane) - 1)); }
 
 struct V3Params {
-    const int32_t *A;
-    const int32_t *AT;
+    const int32_t *A;      // nr x n (row stride n)
+    const int32_t *AT;     // n x nr (row stride nr)
     int32_t *tau;          // in: start assignment; out: final assignment
     const int32_t *sigma;  // start inverse assignment
     const int32_t *d;      // start benefits d[c] = a[c][tau(c)]
@@ -217,6 +217,7 @@ struct V3Params {
     const int32_t *flags;  // [0] != 0: range check failed, do nothing
     int32_t *err;          // set when a wait exceeds its spin limit (1) or a decision is invalid (2)
     int n;
+    int nr;  // real agents; agents nr..n-1 are virtual (benefit 0 everywhere, no candidate list)
     int64_t max_switches;
 };
 
@@ -224,8 +225,9 @@ __device__ __forceinline__ void put_word(u64 *p, u64 w) {
     __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// NPER: gathered words per thread (G * kW <= NPER * kT).
-template <int NPER>
+// NPER: gathered words per thread (G * kW <= NPER * kT).  VIRT: the instance
+// has virtual agents (nr < n; the square path compiles without their tests).
+template <int NPER, bool VIRT>
 __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
     extern __shared__ __align__(16) u64 wl[];  // gathered words, G x (words of the round)
     // values reduced by this workgroup in a round: 0 best keys, 1 pending keys, 2 + j the
@@ -246,10 +248,12 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
     __shared__ int s_err;
 
     if (P.flags[0]) return;  // same decision in every workgroup
-    const int G = gridDim.x, q = blockIdx.x, t = threadIdx.x, n = P.n;
-    const int64_t nn = n;
+    const int G = gridDim.x, q = blockIdx.x, t = threadIdx.x, n = P.n, nr = VIRT ? P.nr : P.n;
+    const int64_t nn = n, nt_ = VIRT ? (int64_t)nr : nn;  // row strides of A and of AT
     const int r = q * kT + t;
     const bool mine = r < n;
+    const bool real = VIRT ? r < nr : mine;  // a virtual agent keeps no list: its exchanges are the real agents' moves
+    auto is_real = [&](int x) { return !VIRT || x < nr; };
     const int lane = t & 63, wave = t >> 6;
 
     int tr = 0, dr = 0;
@@ -261,6 +265,8 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
     if (mine) {
         tr = P.tau[r];
         dr = P.d[r];
+    }
+    if (real) {
 #pragma unroll
         for (int i = 0; i < kM && i < kScanListLen; ++i) {
             const u64 k = P.lists[(size_t)r * kScanListLen + i];
@@ -538,10 +544,19 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         if (mine && !stall) tr2 = r == is ? js : (r == k ? j0 : tr);
         int a1 = 0, a2 = 0, w1 = 0, w2 = 0;
         if (mine && !stall && r != is && r != k) {
-            a1 = P.AT[(int64_t)js * nn + r];  // a[r][j*]
-            a2 = P.AT[(int64_t)j0 * nn + r];  // a[r][j0]
-            w1 = P.A[(int64_t)is * nn + tr];  // a[i*][tau(r)]
-            w2 = P.A[(int64_t)k * nn + tr];   // a[k][tau(r)]
+            if (!VIRT) {
+                a1 = P.AT[(int64_t)js * nt_ + r];  // a[r][j*]
+                a2 = P.AT[(int64_t)j0 * nt_ + r];  // a[r][j0]
+                w1 = P.A[(int64_t)is * nn + tr];   // a[i*][tau(r)]
+                w2 = P.A[(int64_t)k * nn + tr];    // a[k][tau(r)]
+            } else {
+                if (real) {
+                    a1 = P.AT[(int64_t)js * nt_ + r];
+                    a2 = P.AT[(int64_t)j0 * nt_ + r];
+                }
+                w1 = P.A[(int64_t)is * nn + tr];
+                if (k < nr) w2 = P.A[(int64_t)k * nn + tr];
+            }
         }
         // (No branch may merge paths that hold loaded values in different registers: the
         // copy at the merge would wait for the loads.)
@@ -552,14 +567,14 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             const bool ok = dd < nref && mine && x != is && x != k && r != x;
             ra[dd] = rb[dd] = 0;
             if (ok) {
-                ra[dd] = P.AT[(int64_t)nx_tau[dd] * nn + r];  // a[r][tau(x)]
-                rb[dd] = P.A[(int64_t)x * nn + tr2];          // a[x][tau(r)] after the switch
+                if (real) ra[dd] = P.AT[(int64_t)nx_tau[dd] * nt_ + r];  // a[r][tau(x)] (real == mine unless VIRT)
+                rb[dd] = P.A[(int64_t)x * nn + tr2];                     // a[x][tau(r)] after the switch
             }
         }
         int dis = 0, dk = 0;
         if (!stall) {
             dis = P.A[(int64_t)is * nn + js];  // a[i*][j*]
-            dk = P.A[(int64_t)k * nn + j0];    // a[k][j0]
+            if (is_real(k)) dk = P.A[(int64_t)k * nn + j0];  // a[k][j0]
         }
 
         // ---- owners rebuild the lists of this round's targets (while the loads are in flight)
@@ -623,7 +638,7 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         // Targets of the next round: i* (share g(r, i*)), k (g(r, k)), then the live pending
         // agents chosen in this round.  Shares go straight to vals.
         int2 *tgn = tgc[(s + 1) & 1];
-        int jn = 0;
+        int jn = 0, nsw = 0;  // next round's targets; of them the switch's agents
         if (!stall) {
             ++S;
             gsum += gw;
@@ -635,22 +650,25 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 list_drop_jobs(L, js, j0);
                 list_insert(L, B, le_key(g1, js, is));
                 list_insert(L, B, le_key(g2, j0, k));
+                const bool drop = switched || !real;  // (a virtual agent never keeps a list)
 #pragma unroll
-                for (int i = 0; i < kM; ++i) L[i] = switched ? 0 : L[i];
-                B = switched ? 0 : B;
+                for (int i = 0; i < kM; ++i) L[i] = drop ? 0 : L[i];
+                B = drop ? 0 : B;
                 inflight = switched ? false : inflight;
                 s0 = r == is ? 0 : (r == k ? le_key(-gw, j0, t) : le_key(g1, tr, t));  // g(k, i*) after the switch
                 s1 = r == k ? 0 : (r == is ? le_key(-gw, js, t) : le_key(g2, tr, t));  // g(i*, k) after the switch
                 tr = tr2;
                 dr = r == is ? dis : (r == k ? dk : dr);
             }
+            // a virtual partner keeps no list: only i* is then rebuilt
+            nsw = is_real(k) ? 2 : 1;
             vals[2][t] = s0;
-            vals[3][t] = s1;
+            if (nsw == 2) vals[3][t] = s1;
             if (t == 0) {
                 tgn[0] = make_int2(is, js);
-                tgn[1] = make_int2(k, j0);
+                if (nsw == 2) tgn[1] = make_int2(k, j0);
             }
-            jn = 2;
+            jn = nsw;
         } else {
             ++stalls;
         }
@@ -666,7 +684,7 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 ++jn;
             }
         }
-        refreshes += jn - (stall ? 0 : 2);
+        refreshes += jn - nsw;
         nt = jn;
     }
 
@@ -699,12 +717,16 @@ hipError_t launch_switch_v3(const Instance &I, int64_t max_switches, void *words
     P.flags = I.flags;
     P.err = err;
     P.n = I.n;
+    P.nr = I.nr;
     P.max_switches = max_switches;
     const int grid = switch_v3_grid(I.n);
     if (grid < 1 || grid > kMaxG) return hipErrorInvalidValue;
     const size_t shm = (size_t)grid * kW * sizeof(u64);
     // the narrow gather when every workgroup's words fit 8 per thread
-    const void *kern = grid * kW <= 8 * kT ? (const void *)k_switch_v3<8> : (const void *)k_switch_v3<kGatherPer>;
+    const bool narrow = grid * kW <= 8 * kT, virt = I.nr < I.n;
+    const void *kern = narrow ? (virt ? (const void *)k_switch_v3<8, true> : (const void *)k_switch_v3<8, false>)
+                              : (virt ? (const void *)k_switch_v3<kGatherPer, true>
+                                      : (const void *)k_switch_v3<kGatherPer, false>);
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     void *args[] = {&P};
