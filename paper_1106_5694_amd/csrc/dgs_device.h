@@ -79,6 +79,14 @@ __device__ __forceinline__ u64 shfl_xor64(u64 v, int mask) {
     return ((u64)(uint32_t)hi << 32) | (u64)(uint32_t)lo;
 }
 
+// Maximum over the wave, every lane gets it (all lanes active).
+template <int M = 32>
+__device__ __forceinline__ u64 wave_max64(u64 v) {
+    v = umax64(v, xor_lanes64<M>(v));
+    if constexpr (M > 1) return wave_max64<M / 2>(v);
+    return v;
+}
+
 // Lane `lane`'s value (lane uniform across the wave), through SGPRs.
 __device__ __forceinline__ u64 readlane64(u64 v, int lane) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);

@@ -201,11 +201,8 @@ __global__ __launch_bounds__(256) void k_scan_best(const u64 *__restrict__ part,
         m = umax64(m, p[2 * x]);
         y = umax64(y, p[2 * x + 1]);
     }
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        m = umax64(m, shfl_xor64(m, s));
-        y = umax64(y, shfl_xor64(y, s));
-    }
+    m = wave_max64(m);
+    y = wave_max64(y);
     if (lane == 0) {
         bk[r] = m;
         ba[r] = y;
@@ -243,8 +240,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const u64 *__restrict__ par
     } else {
         for (int x = lane; x < nb; x += 64) bnd = umax64(bnd, p[2 * x + 1]);
     }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) bnd = umax64(bnd, shfl_xor64(bnd, m));
+    bnd = wave_max64(bnd);
     // up to kListLen + 1 rounds of "largest block best above the bound"
     u64 taken_max = ~(u64)0;  // keys already emitted are >= this
     u64 out = 0;              // lane i < kListLen keeps entry i
@@ -261,8 +257,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const u64 *__restrict__ par
                 if (k > bnd && k < taken_max) m1 = umax64(m1, k);
             }
         }
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) m1 = umax64(m1, shfl_xor64(m1, m));
+        m1 = wave_max64(m1);
         if (m1 == 0) break;
         if (round == kListLen) {
             bnd = m1;  // the next block best above B becomes the bound
