@@ -21,9 +21,9 @@ Contents:
     ``rect_dgs_full`` the same in C (``orc_rect_dgs``) for larger sizes,
     and ``global_greedy`` (``orc_global_greedy``) the global greedy start
     (largest remaining entry first).
-  * ``lazy_dgs`` (below) -- Algorithm 1 as printed (stale bests of agents
-    and jobs, the branch rule, the improvement guard, repeated passes),
-    with numpy row evaluations.
+  * ``lazy_dgs`` (below) -- lazy DGS, Algorithm 1 (stale stored bests of
+    agents and jobs, the selection rule, the improvement guard, repeated
+    passes), with numpy row evaluations.
 
 Every function computes in int64.  Parity unpinned: none -- each function
 is pinned by the tests listed in the repository's design notes.
@@ -168,30 +168,33 @@ def dgs_incr(A, init=None, max_switches=-1, trace_cap=0):
     return _run(lib().orc_dgs_incr, A, init, max_switches, trace_cap, True)
 
 
+def _claim_in_order(pairs):
+    """Walk candidate exchanges (pairs of agents) in the given order; keep a
+    pair when neither agent is claimed by a pair kept before it, and claim
+    both.  Returns the positions of the kept pairs."""
+    claimed, kept = set(), []
+    for pos, (x, y) in enumerate(pairs):
+        if x not in claimed and y not in claimed:
+            claimed.update((x, y))
+            kept.append(pos)
+    return kept
+
+
 def check_conflicts(tau, ga, ja, gj, ij):
-    """Check Conflicts (Algorithm 4) on one round's evaluations: agent
-    exchanges (agent i to job ja[i], gain ga[i]) then job exchanges (agent
-    ij[j] to job j, gain gj[j]), each in index order, positive ones only.
-    Both agents of an exchange (for job j: the new agent and the current
-    owner) must be unclaimed for it to be kept; a kept exchange claims both.
-    Returns (kept agent pairs [(i, partner)], kept job pairs [(new agent,
-    owner)])."""
+    """Check Conflicts (Algorithm 4) on one round's evaluations.  The
+    positive agent exchanges (agent i to job ja[i], its owner to tau(i)) in
+    agent order, then the positive job exchanges (agent ij[j] to job j, the
+    owner of j to tau(ij[j])) in job order, each as its pair of agents, go
+    through ``_claim_in_order``.  Returns (kept agent pairs [(i, partner)],
+    kept job pairs [(new agent, owner)])."""
     n = len(tau)
     sigma = np.empty(n, dtype=np.int64)
     sigma[tau] = np.arange(n)
-    claimed = np.zeros(n, dtype=bool)
-    kept_a, kept_j = [], []
-    for i in np.flatnonzero(ga > 0):
-        p = int(sigma[ja[i]])
-        if not (claimed[i] or claimed[p]):
-            claimed[i] = claimed[p] = True
-            kept_a.append((int(i), p))
-    for j in np.flatnonzero(gj > 0):
-        i, o = int(ij[j]), int(sigma[j])
-        if not (claimed[i] or claimed[o]):
-            claimed[i] = claimed[o] = True
-            kept_j.append((i, o))
-    return kept_a, kept_j
+    agent_pairs = [(int(i), int(sigma[ja[i]])) for i in np.flatnonzero(ga > 0)]
+    job_pairs = [(int(ij[j]), int(sigma[j])) for j in np.flatnonzero(gj > 0)]
+    kept = _claim_in_order(agent_pairs + job_pairs)
+    na = len(agent_pairs)
+    return ([agent_pairs[p] for p in kept if p < na], [job_pairs[p - na] for p in kept if p >= na])
 
 
 def parallel_dgs(A, init=None, max_rounds=-1):
@@ -246,54 +249,78 @@ def _jde_row(A, tau, sigma, j):
     return (int(g[i]), i) if g[i] > 0 else (0, -1)
 
 
+class _StoredImprovements:
+    """The stored improvements of lazy DGS (Section 3.3, Algorithm 1): for
+    every agent its best exchange (ADE, Algorithm 2) and for every job its
+    best exchange (the job side), kept only when the gain is positive, and
+    left as they are until refreshed (so they may be stale)."""
+
+    def __init__(self, A64, tau, sigma):
+        n = A64.shape[0]
+        self.A, self.n = A64, n
+        self.agent = [_ade_row(A64, tau, sigma, i) for i in range(n)]   # (value, job)
+        self.job = [_jde_row(A64, tau, sigma, j) for j in range(n)]     # (value, agent)
+        self.va = np.array([v for v, _ in self.agent], dtype=np.int64)
+        self.vj = np.array([v for v, _ in self.job], dtype=np.int64)
+
+    def any_positive(self):
+        return self.n > 1 and (self.va.max() > 0 or self.vj.max() > 0)
+
+    def take(self):
+        """The selection rule: the largest agent value and the largest job
+        value (lowest index among equals on each side); the agent's exchange
+        is followed only when its value is strictly larger.  The followed
+        entry is cleared.  Returns the exchange as (agent, job)."""
+        a, b = int(np.argmax(self.va)), int(np.argmax(self.vj))
+        if self.va[a] > self.vj[b]:
+            pair = (a, self.agent[a][1])
+            self.va[a], self.agent[a] = 0, (0, -1)
+        else:
+            pair = (self.job[b][1], b)
+            self.vj[b], self.job[b] = 0, (0, -1)
+        return pair
+
+    def refresh(self, tau, sigma, agents, jobs):
+        for x in agents:
+            self.agent[x] = _ade_row(self.A, tau, sigma, x)
+            self.va[x] = self.agent[x][0]
+        for y in jobs:
+            self.job[y] = _jde_row(self.A, tau, sigma, y)
+            self.vj[y] = self.job[y][0]
+
+
 def lazy_dgs(A, init=None, max_switches=-1):
-    """Algorithm 1 as printed.  Each pass evaluates every agent (ADE) and
-    every job (JDE) and stores their best positive improvements; then, while
-    a stored improvement is positive, it takes the agent i* and the job j*
-    with the largest stored values (lowest index on ties), follows i*'s
-    stored exchange if its value is strictly larger than j*'s, else j*'s,
-    zeroes the stored value it followed, and applies the exchange only if it
-    raises f, re-evaluating the two agents and the two jobs involved.
-    Passes repeat until one applies nothing; max_switches stops early.
+    """Lazy DGS (Section 3.3, Algorithm 1), numpy.  A pass stores the best
+    positive improvement of every agent and every job
+    (``_StoredImprovements``); exchanges are then taken in the selection
+    order of ``_StoredImprovements.take`` until no stored value is positive.
+    A taken exchange (agent i to job j, the current owner of j to i's job)
+    is applied only if it raises f; after an applied one the two agents and
+    the two jobs it moved are evaluated afresh, every other stored value
+    stays as it was.  Passes repeat until one applies nothing; max_switches
+    bounds the applied exchanges and is checked before every attempt.
     Returns dict(tau, f, S = switches applied, attempts, passes)."""
     A64 = _mat(A).astype(np.int64)
     n = A64.shape[0]
-    tau = greedy(A) if init is None else np.array(init, dtype=np.int32, copy=True)
-    tau = tau.astype(np.int64)
+    tau = (greedy(A) if init is None else np.array(init, dtype=np.int32, copy=True)).astype(np.int64)
+    sigma = np.empty(n, dtype=np.int64)
     S = attempts = passes = 0
     while max_switches < 0 or S < max_switches:
         passes += 1
-        sigma = np.empty(n, dtype=np.int64)
         sigma[tau] = np.arange(n)
-        up = [_ade_row(A64, tau, sigma, i) for i in range(n)]
-        lo = [_jde_row(A64, tau, sigma, j) for j in range(n)]
-        dup = np.array([d for d, _ in up], dtype=np.int64)
-        dlo = np.array([d for d, _ in lo], dtype=np.int64)
+        stored = _StoredImprovements(A64, tau, sigma)
         applied = 0
-        while n > 1 and (dup.max() > 0 or dlo.max() > 0):
-            if 0 <= max_switches <= S:
-                break
+        while stored.any_positive() and not (0 <= max_switches <= S):
             attempts += 1
-            istar, jstar = int(np.argmax(dup)), int(np.argmax(dlo))
-            if dup[istar] > dlo[jstar]:
-                i, j = istar, up[istar][1]
-                dup[istar], up[istar] = 0, (0, -1)
-            else:
-                i, j = lo[jstar][1], jstar
-                dlo[jstar], lo[jstar] = 0, (0, -1)
+            i, j = stored.take()
             k, t0 = int(sigma[j]), int(tau[i])
-            gain = A64[i, j] + A64[k, t0] - A64[i, t0] - A64[k, j]
-            if gain > 0:
-                tau[i], tau[k] = j, t0
-                sigma[j], sigma[t0] = i, k
-                S += 1
-                applied += 1
-                for x in (i, k):
-                    up[x] = _ade_row(A64, tau, sigma, x)
-                    dup[x] = up[x][0]
-                for y in (j, t0):
-                    lo[y] = _jde_row(A64, tau, sigma, y)
-                    dlo[y] = lo[y][0]
+            if A64[i, j] + A64[k, t0] - A64[i, t0] - A64[k, j] <= 0:
+                continue  # f would not rise: the exchange is dropped
+            tau[i], tau[k] = j, t0
+            sigma[j], sigma[t0] = i, k
+            S += 1
+            applied += 1
+            stored.refresh(tau, sigma, (i, k), (j, t0))
         if applied == 0:
             break
     tau = tau.astype(np.int32)

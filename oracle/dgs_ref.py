@@ -26,7 +26,7 @@ exactly) on many small random instances.
     applied at once
   * rectangular DGS (n agents, m >= n jobs): steepest ascent over swaps
     with other agents and moves to unassigned jobs
-  * lazy DGS (Algorithm 1 as printed): stale per-agent and per-job bests,
+  * lazy DGS (Algorithm 1 with stale stored bests): stale per-agent and per-job bests,
     the paper's branch rule and improvement guard, re-evaluation of the two
     agents and two jobs of an applied switch only, full passes repeated
     until a pass applies nothing
@@ -111,6 +111,19 @@ def dgs(A, init=None, max_switches=-1):
     return tau, objective(A, tau), S, trace
 
 
+def claim_in_order(pairs):
+    """Keep each pair of agents, in the given order, unless one of its two
+    agents was claimed by a pair kept before it; a kept pair claims both.
+    Returns a list of booleans (kept or not) for the pairs."""
+    claimed, out = set(), []
+    for x, y in pairs:
+        ok = x not in claimed and y not in claimed
+        if ok:
+            claimed.update((x, y))
+        out.append(ok)
+    return out
+
+
 def check_conflicts(rb, jb, tau):
     """Check Conflicts (Algorithm 4) over one round's fresh evaluations.
 
@@ -118,35 +131,22 @@ def check_conflicts(rb, jb, tau):
     agent) of job j's best exchange (JDE).  A positive agent exchange moves
     agent i to job j_i and the current owner sigma(j_i) to tau(i); a positive
     job exchange gives job j to agent i_j and moves the current owner sigma(j)
-    to tau(i_j).  Either one involves exactly two agents.  Agents are looked
-    at first, in index order, then jobs, in index order; an exchange is kept
-    when neither of its two agents has been claimed by an exchange kept before
-    it, and a kept exchange claims both.  A conflict drops only the exchange
-    that has it.
+    to tau(i_j).  Either one involves exactly two agents.  The agent
+    exchanges in agent order, then the job exchanges in job order, go through
+    ``claim_in_order``: a conflict drops only the exchange that has it.
 
     Returns (kept agent exchanges [(i, partner)], kept job exchanges
     [(j, new agent, owner)], conflicting agents, conflicting jobs)."""
     sigma = inverse(tau)
-    claimed = set()
-    kept_a, kept_j, conf_a, conf_j = [], [], [], []
-    for i, (g, j) in enumerate(rb):
-        if g is None or g <= 0:
-            continue
-        pair = (i, sigma[j])
-        if claimed.intersection(pair):
-            conf_a.append(i)
-        else:
-            claimed.update(pair)
-            kept_a.append(pair)
-    for j, (g, i) in enumerate(jb):
-        if g is None or g <= 0:
-            continue
-        pair = (i, sigma[j])
-        if claimed.intersection(pair):
-            conf_j.append(j)
-        else:
-            claimed.update(pair)
-            kept_j.append((j, i, sigma[j]))
+    agents = [i for i, (g, _) in enumerate(rb) if g is not None and g > 0]
+    jobs = [j for j, (g, _) in enumerate(jb) if g is not None and g > 0]
+    pairs = [(i, sigma[rb[i][1]]) for i in agents] + [(jb[j][1], sigma[j]) for j in jobs]
+    keep = claim_in_order(pairs)
+    na = len(agents)
+    kept_a = [pairs[p] for p in range(na) if keep[p]]
+    conf_a = [agents[p] for p in range(na) if not keep[p]]
+    kept_j = [(jobs[p - na], pairs[p][0], pairs[p][1]) for p in range(na, len(pairs)) if keep[p]]
+    conf_j = [jobs[p - na] for p in range(na, len(pairs)) if not keep[p]]
     return kept_a, kept_j, conf_a, conf_j
 
 
@@ -200,38 +200,57 @@ def jde(A, tau, j):
     return best, bi
 
 
+def stored_improvements(A, tau):
+    """Lazy DGS's stored values (Section 3.3, Algorithm 1): every agent's and
+    every job's best exchange, positive improvements only."""
+    n = len(A)
+    return ([best_positive(ade(A, tau, i)) for i in range(n)],
+            [best_positive(jde(A, tau, j)) for j in range(n)])
+
+
+def take_stored(agent_vals, job_vals):
+    """The selection rule: the largest agent value and the largest job value
+    (lowest index on ties on each side); the agent's exchange only when its
+    value is strictly larger.  Clears the entry taken and returns the exchange
+    as (agent, job)."""
+    n = len(agent_vals)
+    a = max(range(n), key=lambda i: (agent_vals[i][0], -i))
+    b = max(range(n), key=lambda j: (job_vals[j][0], -j))
+    if agent_vals[a][0] > job_vals[b][0]:
+        pair = (a, agent_vals[a][1])
+        agent_vals[a] = (0, -1)
+    else:
+        pair = (job_vals[b][1], b)
+        job_vals[b] = (0, -1)
+    return pair
+
+
 def lazy_dgs(A, init=None, max_switches=-1):
-    """Algorithm 1 as printed.  Returns (tau, f, S, attempts, passes)."""
+    """Lazy DGS (Section 3.3, Algorithm 1): passes of stored improvements
+    taken in the selection order, each exchange applied only when it raises
+    f, the two agents and two jobs of an applied exchange evaluated afresh.
+    Returns (tau, f, S, attempts, passes)."""
     n = len(A)
     tau = list(greedy(A) if init is None else init)
     S = attempts = passes = 0
     while max_switches < 0 or S < max_switches:
         passes += 1
-        up = [best_positive(ade(A, tau, i)) for i in range(n)]   # (delta-bar_i, j_i)
-        lo = [best_positive(jde(A, tau, j)) for j in range(n)]   # (delta_j, i_j)
+        agent_vals, job_vals = stored_improvements(A, tau)
         applied = 0
-        while max(d for d, _ in up) > 0 or max(d for d, _ in lo) > 0:
-            if 0 <= max_switches <= S:
-                break
+        while max(v for v, _ in agent_vals + job_vals) > 0 and not (0 <= max_switches <= S):
             attempts += 1
-            istar = max(range(n), key=lambda i: (up[i][0], -i))
-            jstar = max(range(n), key=lambda j: (lo[j][0], -j))
-            if up[istar][0] > lo[jstar][0]:
-                i, j = istar, up[istar][1]
-                up[istar] = (0, -1)
-            else:
-                i, j = lo[jstar][1], jstar
-                lo[jstar] = (0, -1)
+            i, j = take_stored(agent_vals, job_vals)
             k, t0 = inverse(tau)[j], tau[i]
             new = switch(i, j, tau)
-            if objective(A, new) > objective(A, tau):
-                tau = new
-                S += 1
-                applied += 1
-                for x in (i, k):
-                    up[x] = best_positive(ade(A, tau, x))
-                for y in (j, t0):
-                    lo[y] = best_positive(jde(A, tau, y))
+            if objective(A, new) <= objective(A, tau):
+                continue
+            tau = new
+            S += 1
+            applied += 1
+            for x in (i, k):
+                agent_vals[x] = best_positive(ade(A, tau, x))
+            for y in (j, t0):
+                job_vals[y] = best_positive(jde(A, tau, y))
         if applied == 0:
             break
     return tau, objective(A, tau), S, attempts, passes

@@ -35,7 +35,7 @@ the n = 16384 low-rank workload (1000 providers, 16384 receivers, seed 1),
 from the agent-order greedy start and from the global greedy start.
 
 With ``--lazy`` it writes tests/golden/lowrank16384_lazy.txt: the oracle's
-lazy DGS (Algorithm 1 as printed) from the greedy start of the n = 16384
+lazy DGS (Algorithm 1 with stale stored bests) from the greedy start of the n = 16384
 workload, seed 1.
 """
 from __future__ import annotations
@@ -148,7 +148,7 @@ def parallel(seeds=(1, 2)):
 
 
 def lazy(seeds=(1,)):
-    lines = ["# Oracle lazy DGS (Algorithm 1 as printed: stale agent and job bests, strict",
+    lines = ["# Oracle lazy DGS (Algorithm 1 with stale stored bests: stale agent and job bests, strict",
              "# branch rule, improvement guard, passes until one applies nothing) on the",
              "# n = 16384 low-rank-plus-noise workload (workloads.gen.lowrank_matrix(16384, seed)),",
              "# greedy start; written by make_golden.py --lazy.  tau_sha256 as in lowrank16384.txt."]

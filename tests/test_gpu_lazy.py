@@ -1,4 +1,4 @@
-"""GPU parity of lazy DGS (Algorithm 1 as printed).
+"""GPU parity of lazy DGS (Algorithm 1 with stale stored bests).
 
 The HIP path (dgs_solve_ex with DGS_LAZY, through the C ABI) against
 oracle.lazy_dgs, bit-exact: the same assignment, total benefit, switches,

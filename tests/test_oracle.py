@@ -395,7 +395,7 @@ def test_parallel_prefix_and_resume():
     assert g.max() <= 0
 
 
-# Lazy DGS (Algorithm 1 as printed), worked by hand from the identity start
+# Lazy DGS (Algorithm 1 with stale stored bests), worked by hand from the identity start
 # (f = 13).  Pass 1: stored agent bests (6, job 2), (5, job 0), (6, job 0) and
 # job bests (6, agent 2), (5, agent 0), (6, agent 0) (job 1: agents 0 and 2
 # tie at 5, the lower agent is kept).  Attempt 1: the maxima tie at 6 and the
