@@ -81,7 +81,7 @@ typedef enum dgs_status {
  * rescans and stalls stay 0, and device_ms also spans the host's read of
  * each round's (pass's) count. */
 #define DGS_PARALLEL 0x8u
-/* dgs_solve_ex: lazy DGS, Algorithm 1 as printed.  Each pass evaluates every
+/* dgs_solve_ex: lazy DGS, Algorithm 1 with stale stored bests.  Each pass evaluates every
  * agent (best job, lowest job on ties) and every job (best agent to take it,
  * lowest agent on ties) and stores the positive improvements; then, while a
  * stored improvement is positive, it follows the agent's stored exchange if

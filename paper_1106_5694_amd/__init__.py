@@ -182,7 +182,7 @@ def solve(A, init=None, max_switches: int = -1, profile: bool = False, parallel:
     parallel: Parallel DGS (Algorithm 3 with Check Conflicts, Algorithm 4):
     every round applies all non-conflicting improving exchanges at once;
     max_switches then bounds the rounds (result["rounds"]).
-    lazy: Algorithm 1 as printed (stale agent and job bests, the paper's
+    lazy: Algorithm 1 with stale stored bests (stale agent and job bests, the paper's
     branch rule and improvement guard); result["rounds"] = passes,
     result["attempts"] = exchanges tried.
     global_greedy: start from the global greedy assignment (largest

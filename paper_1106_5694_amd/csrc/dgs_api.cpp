@@ -314,7 +314,7 @@ struct Call {
     bool profile;
     bool coop = true;  // cooperative switching launch (else the caller owns co-residency)
     bool parallel = false;  // Parallel DGS rounds instead of the switching loop (max_switches = max rounds)
-    bool lazy = false;      // lazy DGS passes (Algorithm 1 as printed) instead of the switching loop
+    bool lazy = false;      // lazy DGS passes (Algorithm 1 with stale stored bests) instead of the switching loop
     hipMemPool_t pool = nullptr;  // device buffers from this pool (stream-ordered) instead of the cache
     Workspace *ws = nullptr;      // a workspace the caller holds (not taken from or returned to the cache)
     HostRes *host = nullptr;      // host resources the caller holds (likewise)
@@ -344,24 +344,37 @@ dgs_status parallel_rounds(const Instance &I, HostRes *h, int64_t max_rounds, in
     return DGS_OK;
 }
 
-// Lazy DGS (Algorithm 1 as printed): passes of a full evaluation of agents
-// (into I.bk) and jobs (per owner agent, into I.bb, free in this mode)
-// followed by the single-workgroup switching phase, until a pass applies
-// nothing or max_switches is reached.  d must be current; the passes keep it.
-dgs_status lazy_passes(const Instance &I, HostRes *h, int64_t max_switches, int64_t *passes_out, hipStream_t s) {
+// Lazy DGS (Algorithm 1 with stale stored bests): passes of a full
+// evaluation of agents (into I.bk) and jobs (per owner agent, into I.bb,
+// free in this mode) followed by the switching phase of the pass (one
+// cooperative launch), until a pass applies nothing or max_switches is
+// reached.  d must be current; the passes keep tau, sigma and d.
+dgs_status lazy_passes(const Instance &I, HostRes *h, int64_t max_switches, bool coop, int64_t *passes_out,
+                       hipStream_t s) {
     int64_t passes = 0, S = 0;
     int64_t *hs = h->stats + 10;  // [0..5] = stats[0..5]
-    while (max_switches < 0 || S < max_switches) {
+    if (lazy_word_bytes(I.n) > switch_v3_word_bytes(I.n)) {
+        set_error("internal: lazy exchange words do not fit");
+        return DGS_E_DEVICE;
+    }
+    while (I.n >= 2 && (max_switches < 0 || S < max_switches)) {
         DGS_HIP(launch_scan_best_transposed(I, I.scan, s, I.bk, nullptr, I.bb));
         ++passes;
-        DGS_HIP(launch_lazy_pass(I, I.bb, max_switches, s));
-        int32_t *err = (int32_t *)(h->stats + 9);  // rewritten by the final flags copy
-        DGS_HIP(hipMemcpyAsync(hs, I.stats, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        DGS_HIP(hipMemcpyAsync(err, I.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        DGS_HIP(hipStreamSynchronize(s));
-        S = hs[0];
-        if (hs[5] == 0 || *err != 0) break;  // a broken invariant is reported by the caller
+        DGS_HIP(launch_fill((int32_t *)I.words, (int32_t)(lazy_word_bytes(I.n) / 4), -1, s));
+        {
+            // the cooperative pass holds the whole device
+            std::unique_lock<std::mutex> lk(g_ctx.loop_mu, std::defer_lock);
+            if (coop) lk.lock();
+            DGS_HIP(launch_lazy_pass(I, I.bb, I.words, max_switches, s));
+            int32_t *err = (int32_t *)(h->stats + 9);  // rewritten by the final flags copy
+            DGS_HIP(hipMemcpyAsync(hs, I.stats, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            DGS_HIP(hipMemcpyAsync(err, I.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            DGS_HIP(hipStreamSynchronize(s));
+            S = hs[0];
+            if (hs[5] == 0 || *err != 0) break;  // a broken invariant is reported by the caller
+        }
     }
+    if (I.n < 2) passes = 1;  // one pass that finds nothing to store
     *passes_out = passes;
     return DGS_OK;
 }
@@ -441,7 +454,19 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         int64_t gg_rounds = 0;
         DGS_HIP(run_global_greedy(A, I.AT, nr, n, I.tau, I.sigma, I.glob, h->stats + 12, &gg_rounds, s));
     } else {
-        DGS_HIP(launch_greedy_rounds(A, nr, n, I.tau, I.sigma, I.greedy, I.flags + 2, s));
+        // the persistent greedy holds the whole device, like the switching loop
+        std::unique_lock<std::mutex> lk(g_ctx.loop_mu, std::defer_lock);
+        if (c.coop) lk.lock();
+        DGS_HIP(launch_greedy_rounds(A, nr, n, I.tau, I.sigma, I.greedy, I.flags + 2, c.coop, s));
+        if (c.coop) {  // finished before another solve may take the device; a failed start stops here
+            int32_t *gerr = (int32_t *)(h->stats + 12);
+            DGS_HIP(hipMemcpyAsync(gerr, I.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            DGS_HIP(hipStreamSynchronize(s));
+            if (*gerr) {
+                set_error("internal device check failed in the greedy start (code %d)", *gerr);
+                return DGS_E_DEVICE;
+            }
+        }
     }
     DGS_HIP(mark(DGS_PHASE_LAYOUT));
     if (!gg) DGS_HIP(launch_transpose(A, I.AT, nr, n, s));
@@ -457,7 +482,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
         st = parallel_rounds(I, h, c.max_switches, &rounds, s);
         if (st != DGS_OK) return st;
     } else if (mode == Mode::Solve && c.lazy) {
-        st = lazy_passes(I, h, c.max_switches, &rounds, s);
+        st = lazy_passes(I, h, c.max_switches, c.coop, &rounds, s);
         if (st != DGS_OK) return st;
     } else if (mode == Mode::Solve) {
         // The loops exit at once when the range check failed.  n = 1 has no

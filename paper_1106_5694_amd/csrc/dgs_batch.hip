@@ -47,8 +47,7 @@ struct Red {
 // barrier per call suffices.
 template <int BLOCK>
 __device__ __forceinline__ u64 bmax1(u64 v, u64 *red, int &slot) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = umax64(v, shfl_xor64(v, m));
+    v = wave_max64(v);
     u64 *row = red + slot * Red<BLOCK>::W;
     slot ^= 1;
     if ((threadIdx.x & 63) == 0) row[threadIdx.x >> 6] = v;
@@ -61,8 +60,7 @@ __device__ __forceinline__ u64 bmax1(u64 v, u64 *red, int &slot) {
 
 template <int BLOCK>
 __device__ __forceinline__ void btop2(u64 &a1, u64 &a2, u64 *red, int &slot) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) top2_merge(a1, a2, shfl_xor64(a1, m), shfl_xor64(a2, m));
+    wave_top2(a1, a2);
     u64 *row = red + slot * 2 * Red<BLOCK>::W;
     slot ^= 1;
     if ((threadIdx.x & 63) == 0) {
@@ -145,8 +143,7 @@ __device__ __forceinline__ void wave_eval_row(const int32_t *A, const int32_t *A
         const int c = lane + 64 * u;
         if (c < n && c != r) top2_push(b1, b2, mk_key((arow[rt[c]] + tv[u]) - (dr + rd[c]), rt[c]));
     }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) top2_merge(b1, b2, shfl_xor64(b1, m), shfl_xor64(b2, m));
+    wave_top2(b1, b2);
 }
 
 template <int BLOCK>

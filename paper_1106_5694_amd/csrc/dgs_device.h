@@ -137,12 +137,28 @@ __device__ __forceinline__ void best2_merge(Best2 &a, u64 k1, u64 k2, int c1) {
     }
 }
 
+// Wave reductions over the lane distances M, M / 2, ..., 1 as template
+// arguments: every exchange is a VALU lane permute whatever the compiler's
+// unrolling does (a distance known only at run time goes through the LDS).
+// Every lane of the wave must be active; every lane gets the result.
+template <int M = 32>
+__device__ __forceinline__ void wave_top2(u64 &b1, u64 &b2) {
+    top2_merge(b1, b2, xor_lanes64<M>(b1), xor_lanes64<M>(b2));
+    if constexpr (M > 1) wave_top2<M / 2>(b1, b2);
+}
+template <int M = 32>
+__device__ __forceinline__ void wave_best2(Best2 &a) {
+    const u64 o1 = xor_lanes64<M>(a.k1), o2 = xor_lanes64<M>(a.k2);
+    const int oc = (int)xor_lanes<M>((uint32_t)a.c1);
+    best2_merge(a, o1, o2, oc);
+    if constexpr (M > 1) wave_best2<M / 2>(a);
+}
+
 // Block reductions over BLOCK threads (BLOCK a multiple of 64).  `lds`
 // holds at least 3 * BLOCK / 64 u64.  Every thread gets the result.
 template <int BLOCK>
 __device__ u64 block_max(u64 v, u64 *lds) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = umax64(v, shfl_xor64(v, m));
+    v = wave_max64(v);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) lds[w] = v;
@@ -155,8 +171,7 @@ __device__ u64 block_max(u64 v, u64 *lds) {
 
 template <int BLOCK>
 __device__ void block_top2(u64 &b1, u64 &b2, u64 *lds) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) top2_merge(b1, b2, shfl_xor64(b1, m), shfl_xor64(b2, m));
+    wave_top2(b1, b2);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) {
@@ -172,13 +187,7 @@ __device__ void block_top2(u64 &b1, u64 &b2, u64 *lds) {
 
 template <int BLOCK>
 __device__ void block_best2(Best2 &a, u64 *lds) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        u64 o1 = shfl_xor64(a.k1, m);
-        u64 o2 = shfl_xor64(a.k2, m);
-        int oc = __shfl_xor(a.c1, m, 64);
-        best2_merge(a, o1, o2, oc);
-    }
+    wave_best2(a);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) {

@@ -11,6 +11,11 @@
 //      agent takes the first key of its list whose job is still free.  At
 //      most kRound - 1 jobs are taken inside a round, so the list of kRound
 //      keys never runs out: its first free entry is the agent's greedy choice.
+// The single-instance solve runs the same rule as one persistent launch
+// (k_greedy_pipe: lists of agent i from the jobs free once agents < i - 63
+// have picked, computed while earlier agents resolve); the rounds remain for
+// callers that share the device (the batched solver, the server) and for
+// n > 32768.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,44 +34,64 @@ constexpr int kTopkBlock = 64 * kTopkWaves;
 __device__ __forceinline__ u64 kmax(u64 a, u64 b) { return a > b ? a : b; }
 __device__ __forceinline__ u64 kmin(u64 a, u64 b) { return a < b ? a : b; }
 
-// Sort one key per lane, descending across the wave (bitonic network).
+// Bitonic network over the wave, one key per lane.  The block size K and the
+// lane distance J are template arguments, so every exchange is a VALU lane
+// permute (a distance known only at run time would go through the LDS).
+// Stages J, J / 2, ..., 1 of blocks of K lanes; blocks with (lane & K) == 0,
+// and all lanes when K = 64, are ordered descending.
+template <int K, int J>
+__device__ __forceinline__ u64 bitonic_pass(u64 v, int lane) {
+    const u64 o = xor_lanes64<J>(v);
+    const bool desc_block = (lane & K) == 0 || K == 64;
+    const bool lower = (lane & J) == 0;
+    v = (desc_block == lower) ? kmax(v, o) : kmin(v, o);
+    if constexpr (J > 1) return bitonic_pass<K, J / 2>(v, lane);
+    return v;
+}
+
+// Sort one key per lane, descending across the wave (blocks of 2, 4, ..., 64).
+template <int K = 2>
 __device__ __forceinline__ u64 wave_sort_desc(u64 v, int lane) {
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const u64 o = shfl_xor64(v, j);
-            const bool desc_block = (lane & k) == 0 || k == 64;
-            const bool lower = (lane & j) == 0;
-            v = (desc_block == lower) ? kmax(v, o) : kmin(v, o);
-        }
-    }
+    v = bitonic_pass<K, K / 2>(v, lane);
+    if constexpr (K < 64) return wave_sort_desc<K * 2>(v, lane);
     return v;
 }
 
 // A bitonic sequence across the wave -> sorted descending.
-__device__ __forceinline__ u64 wave_bitonic_desc(u64 v, int lane) {
-#pragma unroll
-    for (int j = 32; j > 0; j >>= 1) {
-        const u64 o = shfl_xor64(v, j);
-        v = ((lane & j) == 0) ? kmax(v, o) : kmin(v, o);
-    }
-    return v;
-}
+__device__ __forceinline__ u64 wave_bitonic_desc(u64 v, int lane) { return bitonic_pass<64, 32>(v, lane); }
 
 // Top kRound of the union of two descending lists (one key per lane each).
 __device__ __forceinline__ u64 wave_merge_top(u64 a, u64 b, int lane) {
     return wave_bitonic_desc(kmax(a, reverse_lanes64(b)), lane);
 }
 
-// The kRound best keys (benefit, job) of the free columns [c0, c1) of row Ar,
+// The kRound best keys (benefit, job) of the free columns [c0, c1) of a row,
 // c1 - c0 <= 64 * kSel, sorted descending across the wave.  Every lane holds
 // its columns' keys in registers; a binary search on the benefit (the high
 // word of the key) finds the largest threshold T with at least kRound keys at
-// or above it: those keys contain the best kRound.  When they number at most
-// 2 kRound they are compacted into `buf` (this wave's 2 x 64 LDS slots) and
-// sorted; otherwise (many equal benefits at T) the keys are merged in batches.
+// or above it.  The best kRound are then the keys above T (fewer than kRound)
+// and, of the keys at T, those of the lowest columns: the first ones in column
+// order c0 + u * 64 + lane, u outer.  They are compacted into `buf` (this
+// wave's 64 LDS slots) and sorted once.
 constexpr int kSel = 16;  // keys per lane
+
+// Wave minimum / maximum (every lane active).
+__device__ __forceinline__ uint32_t wave_min32(uint32_t v) {
+    v = min(v, xor_lanes<32>(v));
+    v = min(v, xor_lanes<16>(v));
+    v = min(v, xor_lanes<8>(v));
+    v = min(v, xor_lanes<4>(v));
+    v = min(v, xor_lanes<2>(v));
+    return min(v, xor_lanes<1>(v));
+}
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v) {
+    v = max(v, xor_lanes<32>(v));
+    v = max(v, xor_lanes<16>(v));
+    v = max(v, xor_lanes<8>(v));
+    v = max(v, xor_lanes<4>(v));
+    v = max(v, xor_lanes<2>(v));
+    return max(v, xor_lanes<1>(v));
+}
 
 __device__ __forceinline__ int count_at_least(const uint32_t (&h)[kSel], uint32_t T) {
     int c = 0;
@@ -75,19 +100,23 @@ __device__ __forceinline__ int count_at_least(const uint32_t (&h)[kSel], uint32_
     return c;
 }
 
-__device__ u64 wave_top_select(const int32_t *Ar, const uint32_t *taken, int c0, int c1, int lane, u64 *buf) {
+// The entries Ar[c0 + u * 64 + lane], u < kSel, of the columns below c1 (0 past c1).
+__device__ __forceinline__ void row_part_load(const int32_t *Ar, int c0, int c1, int lane, int (&v)[kSel]) {
+#pragma unroll
+    for (int u = 0; u < kSel; ++u) {
+        const int c = c0 + u * 64 + lane;
+        v[u] = c < c1 ? Ar[c] : 0;
+    }
+}
+
+__device__ u64 wave_top_select(const int (&v)[kSel], const uint32_t *taken, int c0, int c1, int lane, u64 *buf) {
     u64 key[kSel];
     uint32_t h[kSel];  // benefit part of each key (0: none)
 #pragma unroll
     for (int u = 0; u < kSel; ++u) {
         const int c = c0 + u * 64 + lane;
-        bool ok = false;
-        int v = 0;
-        if (c < c1) {
-            ok = !((taken[c >> 5] >> (c & 31)) & 1u);
-            v = Ar[c];
-        }
-        key[u] = ok ? mk_key(v, c) : 0;
+        const bool ok = c < c1 && !((taken[c >> 5] >> (c & 31)) & 1u);
+        key[u] = ok ? mk_key(v[u], c) : 0;
         h[u] = (uint32_t)(key[u] >> 32);
     }
     // threshold: the largest T with count(h >= T) >= kRound (T = 1 takes every key)
@@ -99,14 +128,8 @@ __device__ u64 wave_top_select(const int32_t *Ar, const uint32_t *taken, int c0,
             if (h[u]) lo = min(lo, h[u]);
             hi = max(hi, h[u]);
         }
-        // wave-wide min of lo and max of hi
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
-            lo = min(lo, (uint32_t)__shfl_xor((int)lo, m, 64));
-            hi = max(hi, (uint32_t)__shfl_xor((int)hi, m, 64));
-        }
-        lo = __builtin_amdgcn_readfirstlane(lo);
-        hi = __builtin_amdgcn_readfirstlane(hi);
+        lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min32(lo));
+        hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max32(hi));
         // invariant: count(h >= lo) >= kRound; the answer lies in [lo, hi]
         while (lo < hi) {
             const uint32_t mid = lo + (hi - lo + 1) / 2;
@@ -117,29 +140,24 @@ __device__ u64 wave_top_select(const int32_t *Ar, const uint32_t *taken, int c0,
         }
         T = lo;
     }
-    const int C = count_at_least(h, T);
-    if (C <= 2 * kRound) {
-        int base = 0;
-#pragma unroll
-        for (int u = 0; u < kSel; ++u) {
-            const bool sel = h[u] >= T;
-            const unsigned long long m = __ballot(sel);
-            if (sel) buf[base + __popcll(m & ((1ull << lane) - 1))] = key[u];
-            base += __popcll(m);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        const u64 a = lane < C ? buf[lane] : 0;
-        const u64 b = lane + 64 < C ? buf[lane + 64] : 0;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // buf may be reused by the caller
-        return wave_merge_top(wave_sort_desc(a, lane), wave_sort_desc(b, lane), lane);
-    }
-    u64 list = 0;
+    // keys above T all go; of the keys at T, the first `room` in column order
+    const int room = kRound - (T == 0xFFFFFFFFu ? 0 : count_at_least(h, T + 1));
+    const unsigned long long below = (1ull << lane) - 1;
+    int base = 0, ties = 0;
 #pragma unroll
     for (int u = 0; u < kSel; ++u) {
-        const u64 k = h[u] >= T ? key[u] : 0;
-        if (__ballot(k != 0)) list = wave_merge_top(list, wave_sort_desc(k, lane), lane);
+        const bool at = h[u] == T && h[u] != 0;
+        const unsigned long long tm = __ballot(at);
+        const bool sel = h[u] > T || (at && ties + __popcll(tm & below) < room);
+        const unsigned long long m = __ballot(sel);
+        if (sel) buf[base + __popcll(m & below)] = key[u];
+        base += __popcll(m);
+        ties += __popcll(tm);
     }
-    return list;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const u64 a = lane < base ? buf[lane] : 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // buf may be reused by the caller
+    return wave_sort_desc(a, lane);
 }
 
 struct TopkParams {
@@ -162,7 +180,9 @@ __global__ __launch_bounds__(kTopkBlock) void k_greedy_topk(TopkParams P) {
     const int c1 = min(P.n, c0 + sub);
     u64 list = 0;
     if (sub <= 64 * kSel) {
-        list = wave_top_select(Ar, P.taken, c0, c1, lane, cand[w]);
+        int vals[kSel];
+        row_part_load(Ar, c0, c1, lane, vals);
+        list = wave_top_select(vals, P.taken, c0, c1, lane, cand[w]);
     } else {
         // streaming: batches of 64 keys, sorted and merged when many pass the running bound
         u64 lmin = 0;
@@ -286,6 +306,296 @@ __global__ __launch_bounds__(256) void k_greedy_resolve(ResolveParams P) {
     }
 }
 
+// ---- the greedy start as one persistent launch ---------------------------------------
+// Producers and one resolver workgroup run at the same time (a cooperative
+// launch, so all are resident).  Work item (i, q), one producer workgroup:
+// the kRound best keys of agent i over part q of the columns (kPart columns)
+// among the jobs free once agents 0 .. i - kRound have picked; the row's
+// entries are loaded before the picks are awaited.  At most kRound - 1 more
+// jobs are taken before agent i picks, so the list holds agent i's best free
+// job of that part.  In the resolver workgroup, staging waves load the part
+// lists, merge an agent's parts into one sorted list of kRound keys and put
+// it into an LDS ring; the resolver wave walks the agents in order and takes
+// the best key of the agent's list whose job is still free.  Producers learn
+// the picks from the resolver's pick words (throttled by its progress word)
+// and the staging waves read the lists, both with relaxed agent-scope
+// atomics; every word carries its agent (plus one) as a 16-bit tag and the
+// buffers are cleared first, so a word is current exactly when its tag
+// matches and no fence is needed.  n <= kPipeMaxN (16-bit jobs and tags; at
+// most kMaxParts parts).
+constexpr int kPW = 8;                     // waves per workgroup
+constexpr int kPipeT = 64 * kPW;           // threads per workgroup
+constexpr int kPart = kPW * 64 * kSel;     // columns per part (8192)
+constexpr int kRingA = 2 * kRound;         // list slots in device memory (agents in flight <= kRound)
+constexpr int kRingL = kRound;             // agents staged in the resolver's LDS (one merged list each)
+// spin limits (each well above a second): LDS polls, polls of device memory
+constexpr long long kPipeSpin = 1ll << 24, kPipeSpinG = 1ll << 20;
+constexpr int kPipeMaxN = 32768;
+constexpr int kMaxParts = (kPipeMaxN + kPart - 1) / kPart;  // 4
+constexpr int kStage = 8;  // lists in flight per staging wave
+
+struct PipeParams {
+    const int32_t *A;   // rows x n
+    u64 *lists;         // [kRingA][Q][kRound] tagged keys
+    uint32_t *picks;    // [rows] (agent + 1) << 16 | job
+    int *progress;      // agents resolved so far; -1 once the resolver has given up
+    int32_t *tau, *sigma, *err;
+    int rows, n, Q;
+    int A_per;          // agents per batch of a staging wave (A_per * Q <= kStage)
+};
+
+// key (benefit, job) of mk_key -> the same order with the tag in bits 31..16
+// and 0xFFFF - job below (0: none, with the tag).
+__device__ __forceinline__ u64 tag_key(u64 k, uint32_t tag) {
+    if (!k) return (u64)(tag << 16);
+    return (k & 0xFFFFFFFF00000000ull) | (u64)(tag << 16) | (u64)(0xFFFFu - (uint32_t)key_index(k));
+}
+__device__ __forceinline__ uint32_t key_tag(u64 k) { return ((uint32_t)k >> 16) & 0xFFFFu; }
+__device__ __forceinline__ int tkey_job(u64 k) { return (int)(0xFFFFu - ((uint32_t)k & 0xFFFFu)); }
+
+// Stop the pipeline: flag the error; producers learn it from the progress word, the
+// resolver's other waves from `fail`.
+__device__ __forceinline__ void pipe_give_up(const PipeParams &P, int *fail) {
+    atomicOr(P.err, 16);
+    __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (blockIdx.x == 0) __hip_atomic_store(P.progress, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The resolver wave: agents in order, each takes the best key of its staged list whose
+// job is free.  The list is sorted (descending over the lanes), so that key sits in its
+// lowest free lane: one ballot.  The LDS reads of agent i + 1's taken words and of agent
+// i + 2's keys go out before agent i chooses, so no LDS round trip is on the per-agent
+// path; the words of agent i + 1 then miss only agent i's job, which the choice of agent
+// i + 1 excludes by comparison.  The keys of agent i + 2 are read right after its ready
+// flag, without waiting: this wave's LDS accesses complete in order, so when the flag read
+// sees the staged value the key read sees the staged keys (otherwise it is read again
+// once the flag is set).
+__device__ __forceinline__ void pipe_resolve(const PipeParams &P, uint32_t *tk, u64 (*ring)[64], int *rdy, int *done,
+                                             int *fail, int lane) {
+    auto word = [&](u64 k) { return tk[(tkey_job(k) & (kPipeMaxN - 1)) >> 5]; };
+    auto flag = [&](int slot) { return __hip_atomic_load(&rdy[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+    auto wait = [&](int i, int slot) -> bool {  // bounded wait until agent i's list is staged
+        long long spins = 0;
+        while (flag(slot) != i + 1) {
+            if (++spins > kPipeSpin || __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                if (lane == 0) pipe_give_up(P, fail);
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        return true;
+    };
+    auto next = [&](int slot) { return slot + 1 == kRingL ? 0 : slot + 1; };
+    u64 kn = 0;  // keys of agent i + 1
+    if (!wait(0, 0)) return;
+    u64 kc = ring[0][lane];  // keys of agent i
+    uint32_t bc = word(kc);  // taken word of agent i's key, read before agent i - 1 chose
+    if (P.rows > 1) {
+        if (!wait(1, 1)) return;
+        kn = ring[1][lane];
+    }
+    int s2 = next(1);  // slot of agent i + 2
+    int jprev = -1;    // agent i - 1's job
+    for (int i = 0; i < P.rows; ++i) {
+        const uint32_t bn = word(kn);
+        u64 k2 = 0;
+        int f2 = 0;
+        if (i + 2 < P.rows) {
+            f2 = flag(s2);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the key read stays after the flag read
+            k2 = ring[s2][lane];
+        }
+        const int jc = tkey_job(kc);
+        const bool fr = ((uint32_t)(kc >> 32) != 0u) & (((bc >> (jc & 31)) & 1u) == 0u) & (jc != jprev);
+        const unsigned long long m = __ballot(fr);
+        if (m == 0) {  // cannot happen (a list never runs dry); never index with it
+            if (lane == 0) pipe_give_up(P, fail);
+            return;
+        }
+        const int j = tkey_job(readlane64(kc, (int)__builtin_ctzll(m)));
+        if (lane == 0) {
+            atomicOr(&tk[j >> 5], 1u << (j & 31));  // no return value: no wait on the LDS
+            P.tau[i] = j;
+            P.sigma[j] = i;
+            __hip_atomic_store(&P.picks[i], ((uint32_t)(i + 1) << 16) | (uint32_t)j, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(P.progress, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // relaxed: agent i's keys were consumed (used) before this store
+            __hip_atomic_store(done, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        jprev = j;
+        kc = kn;
+        bc = bn;
+        if (i + 2 < P.rows) {
+            if (f2 != i + 3) {
+                if (!wait(i + 2, s2)) return;
+                k2 = ring[s2][lane];
+            }
+            kn = k2;
+        }
+        s2 = next(s2);
+    }
+}
+
+__global__ __launch_bounds__(kPipeT) void k_greedy_pipe(PipeParams P) {
+    __shared__ uint32_t tk[(kPipeMaxN + 31) / 32];  // taken jobs (producer: picks absorbed; resolver: all)
+    __shared__ u64 wl[kPW][64];
+    __shared__ u64 cand[kPW][2 * 64];
+    __shared__ u64 ring[kRingL][64];                // resolver: one merged list per staged agent
+    __shared__ u64 stg[kPW - 1][kStage][64];        // resolver: a staging wave's part lists
+    __shared__ int rdy[kRingL];
+    __shared__ int done, fail;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int words = (P.n + 31) >> 5;
+    for (int x = t; x < words; x += kPipeT) tk[x] = 0;
+    if (t < kRingL) rdy[t] = 0;
+    if (t == 0) {
+        done = 0;
+        fail = 0;
+    }
+    __syncthreads();
+    auto give_up = [&]() { pipe_give_up(P, &fail); };
+
+    if (blockIdx.x == 0) {  // ---- the resolver ----
+        if (w == 0) {
+            pipe_resolve(P, tk, ring, rdy, &done, &fail, lane);
+        } else {
+            // waves 1..kPW-1 stage the lists of batches of A_per consecutive agents: load them
+            // (A_per * Q <= kStage lists in flight per wave) as soon as they are produced, then
+            // copy them into their slots once the consumer is past the slots' previous agents
+            const int Aper = P.A_per;
+            const int nb = (P.rows + Aper - 1) / Aper;
+            for (int b = w - 1; b < nb; b += kPW - 1) {
+                const int k0 = b * Aper, cnt = min(Aper, P.rows - k0);
+                // list e = agent k0 + e / Q, part e % Q
+                const int ne = cnt * P.Q;
+                u64 v[kStage];
+#pragma unroll
+                for (int e = 0; e < kStage; ++e) {
+                    const int k = k0 + e / P.Q, qq = e % P.Q;
+                    v[e] = e < ne ? __hip_atomic_load(&P.lists[((size_t)(k % kRingA) * P.Q + qq) * kRound + lane],
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : 0;
+                }
+                long long spins = 0;
+                for (;;) {
+                    bool ok = true;
+#pragma unroll
+                    for (int e = 0; e < kStage; ++e)
+                        ok &= e >= ne || key_tag(v[e]) == ((uint32_t)(k0 + e / P.Q + 1) & 0xFFFFu);
+                    if (__all(ok)) break;
+                    if (++spins > kPipeSpinG || __hip_atomic_load(&fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                        if (lane == 0) give_up();
+                        return;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                    for (int e = 0; e < kStage; ++e) {
+                        const int k = k0 + e / P.Q, qq = e % P.Q;
+                        if (e < ne && key_tag(v[e]) != ((uint32_t)(k + 1) & 0xFFFFu))
+                            v[e] = __hip_atomic_load(&P.lists[((size_t)(k % kRingA) * P.Q + qq) * kRound + lane],
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                // one list per agent, the top kRound keys over its parts (an agent's keys share
+                // their tag, so tagged keys order as (benefit, -job)), merged in this wave's
+                // LDS area: agent a's list replaces entry a, whose part list is merged by then
+                u64(*sv)[64] = stg[w - 1];
+#pragma unroll
+                for (int e = 0; e < kStage; ++e)
+                    if (e < ne) sv[e][lane] = v[e];
+                if (P.Q > 1) {
+                    for (int a = 0; a < cnt; ++a) {
+                        u64 list = sv[a * P.Q][lane];
+#pragma unroll
+                        for (int f = 1; f < kMaxParts; ++f)  // compile-time stages: lane exchanges on the VALU
+                            if (f < P.Q) list = wave_merge_top(list, sv[a * P.Q + f][lane], lane);
+                        sv[a][lane] = list;
+                    }
+                }
+                spins = 0;
+                while (__hip_atomic_load(&done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= k0 + cnt - 1 - kRingL) {
+                    if (++spins > kPipeSpin || __hip_atomic_load(&fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                        if (lane == 0) give_up();
+                        return;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                for (int a = 0; a < cnt; ++a) ring[(k0 + a) % kRingL][lane] = sv[a][lane];
+                if (lane == 0)
+                    for (int k = k0; k < k0 + cnt; ++k)
+                        // relaxed: this wave's LDS writes of the slot come first, in order
+                        __hip_atomic_store(&rdy[k % kRingL], k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        return;
+    }
+
+    // ---- a producer: items blockIdx.x - 1, + (gridDim.x - 1), ... in order ----
+    const long long items = (long long)P.rows * P.Q, stride = gridDim.x - 1;
+    int absorbed = 0;  // picks of agents < absorbed are in tk
+    for (long long it = blockIdx.x - 1; it < items; it += stride) {
+        const int i = (int)(it / P.Q), q = (int)(it % P.Q);
+        const int need = i - (kRound - 1);  // picks of agents < need must be in tk
+        // the row's entries do not depend on the picks: their loads go out first
+        const int c0 = q * kPart + w * 64 * kSel, c1 = min(P.n, c0 + 64 * kSel);
+        int vals[kSel];
+        row_part_load(P.A + (int64_t)i * P.n, c0, c1, lane, vals);
+        if (need > absorbed) {
+            // one lane waits for the resolver to pass need - 1, napping about 0.2 us per agent
+            // still to resolve (few polls of one word from producers far ahead)
+            if (t == 0) {
+                long long spins = 0;
+                for (;;) {
+                    const int p = __hip_atomic_load(P.progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (p >= need) break;
+                    if (p < 0 || ++spins > kPipeSpinG) {
+                        give_up();
+                        break;
+                    }
+                    const int naps = min(need - p, 16);
+                    for (int z = 0; z < naps; ++z) __builtin_amdgcn_s_sleep(8);
+                }
+            }
+            __syncthreads();
+            if (fail) return;
+        }
+        for (int k = absorbed + t; k < need; k += kPipeT) {
+            long long spins = 0;
+            uint32_t v = __hip_atomic_load(&P.picks[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while ((v >> 16) != ((uint32_t)(k + 1) & 0xFFFFu)) {
+                if (++spins > kPipeSpinG) {
+                    give_up();
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                v = __hip_atomic_load(&P.picks[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            const int j = (int)(v & 0xFFFFu);
+            if (j < P.n) atomicOr(&tk[j >> 5], 1u << (j & 31));
+        }
+        if (need > absorbed) absorbed = need;
+        __syncthreads();
+        if (fail) return;
+        u64 list = c0 < c1 ? wave_top_select(vals, tk, c0, c1, lane, cand[w]) : 0;
+        wl[w][lane] = list;
+#pragma unroll
+        for (int span = 1; span < kPW; span *= 2) {
+            __syncthreads();
+            if (w % (2 * span) == 0) {
+                list = wave_merge_top(list, wl[w + span][lane], lane);
+                wl[w][lane] = list;
+            }
+        }
+        if (w == 0) {
+            u64 *dst = P.lists + ((size_t)(i % kRingA) * P.Q + q) * kRound;
+            __hip_atomic_store(&dst[lane], tag_key(list, (uint32_t)(i + 1) & 0xFFFFu), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();  // wl, cand and tk are reused by the next item
+    }
+}
+
 // The virtual agents rows..n-1 of a rectangular instance take the jobs that
 // no real agent holds (sigma = -1), in increasing job order.  One workgroup:
 // each thread counts the free jobs of its stretch, an exclusive scan in LDS
@@ -363,8 +673,7 @@ __global__ __launch_bounds__(256) void k_gg_heads(GGState P, int round) {
         }
         for (; j < P.cols; j += 64)
             if (P.sigma[j] < 0) best = umax64(best, mk_key(row[j], j));
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) best = umax64(best, shfl_xor64(best, m));
+        best = wave_max64(best);
         h = best ? key_index(best) : -1;  // rows <= cols: a free job always exists
         if (lane == 0) P.head[i] = h;
     }
@@ -382,8 +691,7 @@ __global__ __launch_bounds__(256) void k_gg_cols(GGState P, int round) {
     u64 best = 0;
     for (int i = lane; i < P.rows; i += 64)
         if (P.tau[i] < 0) best = umax64(best, mk_key(col[i], i));
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) best = umax64(best, shfl_xor64(best, m));
+    best = wave_max64(best);
     if (lane == 0) P.colbest[j] = best ? key_index(best) : -1;
 }
 
@@ -453,12 +761,60 @@ hipError_t launch_fill_virtual(int32_t *tau, int32_t *sigma, int32_t rows, int32
     return hipGetLastError();
 }
 
+static int pipe_parts(int n) { return (n + kPart - 1) / kPart; }
+
 size_t greedy_scratch_bytes(int n) {
-    return (size_t)kRound * 64 * sizeof(u64) + (((size_t)n + 31) / 32) * 4 + 256;
+    const size_t rounds = (size_t)kRound * 64 * sizeof(u64) + (((size_t)n + 31) / 32) * 4 + 256;
+    const size_t pipe = (size_t)kRingA * pipe_parts(n) * kRound * sizeof(u64) + (size_t)n * 4 + 512;
+    return rounds > pipe ? rounds : pipe;
+}
+
+// The greedy start as one persistent launch (rows <= n <= kPipeMaxN); false when
+// the device cannot hold the grid (the caller then runs the rounds).
+static bool launch_greedy_pipe(const int32_t *A, int32_t rows, int32_t n, int32_t *tau, int32_t *sigma,
+                               void *scratch, int32_t *err, hipStream_t s, hipError_t *e) {
+    static int cap = -1;
+    if (cap < 0) {
+        int dev = 0, cus = 0, per = 0;
+        cap = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_greedy_pipe, kPipeT, 0) == hipSuccess)
+            cap = cus * per;
+    }
+    const int Q = pipe_parts(n);
+    const long long items = (long long)rows * Q;
+    if (cap < 2 || n > kPipeMaxN) return false;
+    PipeParams P;
+    P.A = A;
+    P.lists = (u64 *)scratch;
+    P.picks = (uint32_t *)((char *)scratch + (size_t)kRingA * Q * kRound * sizeof(u64));
+    P.progress = (int *)((char *)P.picks + (((size_t)rows * 4 + 255) & ~(size_t)255));  // within n * 4 + 512
+    P.tau = tau;
+    P.sigma = sigma;
+    P.err = err;
+    P.rows = rows;
+    P.n = n;
+    P.Q = Q;
+    // a batch is a quarter of the ring at most, so staging runs ahead of the consumer
+    P.A_per = kStage / Q < kRingL / 4 ? kStage / Q : kRingL / 4;
+    if (P.A_per < 1) P.A_per = 1;
+    // tags start at 1: cleared words never match
+    if ((*e = launch_fill((int32_t *)P.lists, kRingA * Q * kRound * 2, 0, s)) != hipSuccess) return true;
+    if ((*e = launch_fill((int32_t *)P.picks, rows, 0, s)) != hipSuccess) return true;
+    if ((*e = launch_fill(P.progress, 1, 0, s)) != hipSuccess) return true;
+    if (rows < n && (*e = launch_fill(sigma, n, -1, s)) != hipSuccess) return true;
+    const long long grid = 1 + (items < cap - 1 ? items : cap - 1);
+    void *args[] = {&P};
+    *e = hipLaunchCooperativeKernel((const void *)k_greedy_pipe, dim3((unsigned)grid), dim3(kPipeT), args, 0, s);
+    if (*e == hipSuccess) *e = launch_fill_virtual(tau, sigma, rows, n, s);
+    return true;
 }
 
 hipError_t launch_greedy_rounds(const int32_t *A, int32_t rows, int32_t n, int32_t *tau, int32_t *sigma,
-                                void *scratch, int32_t *err, hipStream_t s) {
+                                void *scratch, int32_t *err, bool persistent, hipStream_t s) {
+    hipError_t pe = hipSuccess;
+    if (persistent && launch_greedy_pipe(A, rows, n, tau, sigma, scratch, err, s, &pe)) return pe;
     u64 *lists = (u64 *)scratch;
     uint32_t *taken = (uint32_t *)((char *)scratch + (size_t)kRound * 64 * sizeof(u64));
     const int words = (n + 31) / 32;

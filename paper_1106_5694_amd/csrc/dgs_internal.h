@@ -73,12 +73,14 @@ dgs_status ensure_context();            // device, stream and switch-loop grid, 
     } while (0)
 
 hipError_t launch_range_check(const int32_t *A, int64_t count, int32_t *flag, hipStream_t s);
-// Greedy start in rounds (dgs_greedy.hip); scratch of greedy_scratch_bytes(n).
+// Greedy start (dgs_greedy.hip); scratch of greedy_scratch_bytes(n).
 size_t greedy_scratch_bytes(int n);
 // rows agents (0..rows-1) over cols jobs; agents rows..cols-1 then take the
 // jobs left free in increasing order.
+// persistent: one cooperative launch that holds the whole device (callers that
+// do not share the device), else rounds of two launches.
 hipError_t launch_greedy_rounds(const int32_t *A, int32_t rows, int32_t cols, int32_t *tau, int32_t *sigma,
-                                void *scratch, int32_t *err, hipStream_t s);
+                                void *scratch, int32_t *err, bool persistent, hipStream_t s);
 // Virtual agents rows..n-1 take the jobs with sigma = -1 in increasing order.
 hipError_t launch_fill_virtual(int32_t *tau, int32_t *sigma, int32_t rows, int32_t n, hipStream_t s);
 // Global greedy start (largest remaining entry first, lowest agent, then
@@ -170,12 +172,17 @@ int batch_grid_limit(int block);
 int parallel_max_agents();
 hipError_t launch_parallel_round(const Instance &I, int32_t *acc, hipStream_t s);
 
-// Lazy DGS (dgs_lazy.hip): the switching phase of one pass of Algorithm 1 as
-// printed, in one workgroup, for n <= kLazyMaxN.  Reads the pass's evaluation
-// (agent side in I.bk, job side per owner agent in jde); advances stats[0],
-// [1] and [7] (attempts) and sets stats[5] to the switches of the pass.
+// Lazy DGS (dgs_lazy.hip): the switching phase of one pass of Algorithm 1
+// with stale stored bests as one cooperative launch of lazy_grid(n)
+// workgroups, for n <= kLazyMaxN.  Reads the pass's evaluation (agent side
+// in I.bk, job side per owner agent in jde); exchange words of
+// lazy_word_bytes(n) (set to 0xFF first); keeps tau, sigma and d; advances
+// stats[0], [1] and [7] (attempts) and sets stats[5] to the switches of the
+// pass.
 constexpr int kLazyMaxN = 16384;
-hipError_t launch_lazy_pass(const Instance &I, const u64 *jde, int64_t max_switches, hipStream_t s);
+int lazy_grid(int n);
+size_t lazy_word_bytes(int n);
+hipError_t launch_lazy_pass(const Instance &I, const u64 *jde, void *words, int64_t max_switches, hipStream_t s);
 
 hipError_t launch_export_best(const Instance &I, int64_t *gain_out, int32_t *job_out,
                               hipStream_t s);
