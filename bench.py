@@ -41,7 +41,7 @@ SINGLE = {
 }
 WORKLOADS = sorted(SINGLE) + ["batched512", "serving"]
 
-KERNELS = {"range": "k_range_check", "init": "k_greedy_topk+k_greedy_resolve",
+KERNELS = {"range": "k_range_check", "init": "k_greedy_pipe",
            "layout": "k_transpose+k_benefits", "scan": "k_scan_pairs+k_scan_reduce",
            "switch": "k_switch_v3"}
 KERNEL_SOURCES = {"k_switch_v3": "dgs_switch3.hip", "k_scan_pairs+k_scan_reduce": "dgs_scan.hip",
