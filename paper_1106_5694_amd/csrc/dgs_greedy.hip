@@ -337,9 +337,9 @@ constexpr int kStage = 8;  // lists in flight per staging wave
 struct PipeParams {
     const int32_t *A;   // rows x n
     u64 *lists;         // [kRingA][Q][kRound] tagged keys
-    uint32_t *picks;    // [rows] (agent + 1) << 16 | job
+    uint32_t *picks;    // [rows] (agent + 1) << 16 | job; tau and sigma are written from them afterwards
     int *progress;      // agents resolved so far; -1 once the resolver has given up
-    int32_t *tau, *sigma, *err;
+    int32_t *err;
     int rows, n, Q;
     int A_per;          // agents per batch of a staging wave (A_per * Q <= kStage)
 };
@@ -361,22 +361,34 @@ __device__ __forceinline__ void pipe_give_up(const PipeParams &P, int *fail) {
     if (blockIdx.x == 0) __hip_atomic_store(P.progress, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The resolver wave: agents in order, each takes the best key of its staged list whose
-// job is free.  The list is sorted (descending over the lanes), so that key sits in its
-// lowest free lane: one ballot.  The LDS reads of agent i + 1's taken words and of agent
-// i + 2's keys go out before agent i chooses, so no LDS round trip is on the per-agent
-// path; the words of agent i + 1 then miss only agent i's job, which the choice of agent
-// i + 1 excludes by comparison.  The keys of agent i + 2 are read right after its ready
-// flag, without waiting: this wave's LDS accesses complete in order, so when the flag read
-// sees the staged value the key read sees the staged keys (otherwise it is read again
-// once the flag is set).
-__device__ __forceinline__ void pipe_resolve(const PipeParams &P, uint32_t *tk, u64 (*ring)[64], int *rdy, int *done,
-                                             int *fail, int lane) {
-    auto word = [&](u64 k) { return tk[(tkey_job(k) & (kPipeMaxN - 1)) >> 5]; };
-    auto flag = [&](int slot) { return __hip_atomic_load(&rdy[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
-    auto wait = [&](int i, int slot) -> bool {  // bounded wait until agent i's list is staged
+// The resolver wave: agents in order, each takes the first job of its staged list that
+// is free.  The list holds the jobs of the agent's best keys in decreasing key order
+// (0xFFFF: no key), so the first free job is the lowest free lane: one ballot.  The LDS
+// reads of agent i + 1's taken words and of agent i + 2's jobs go out before agent i
+// chooses, so no LDS round trip is on the per-agent path; the words of agent i + 1 then
+// miss only agent i's job, which the choice of agent i + 1 excludes by comparison.  The
+// jobs of agent i + 2 are read right after its ready flag, without waiting: this wave's
+// LDS accesses complete in order, so when the flag read sees the staged value the job
+// read sees the staged jobs (otherwise it is read again once the flag is set).  Every
+// lane runs the stores (the same value to one address, or to a lane's own spare word),
+// so the loop has no branch.  The words of agent i + 1 are read after agent i - 1's job
+// is published, so they miss only agent i's.
+constexpr int kTkWords = (kPipeMaxN + 31) / 32;  // taken bitmap words; 64 spare words follow
+
+__device__ __forceinline__ void pipe_resolve(const PipeParams &P, uint32_t *tk, uint32_t (*ring)[64], int *rdy,
+                                             int *done, int *fail, int lane) {
+    static_assert((kRingL & (kRingL - 1)) == 0, "ring slots by mask");
+    auto word = [&](uint32_t j) { return tk[(j & (kPipeMaxN - 1)) >> 5]; };
+    auto flag = [&](int k) {
+        return __hip_atomic_load(&rdy[k & (kRingL - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    // (an atomic load, so the compiler issues it where it stands, ahead of the choice)
+    auto jobs = [&](int k) {
+        return __hip_atomic_load(&ring[k & (kRingL - 1)][lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    auto wait = [&](int k) -> bool {  // bounded wait until agent k's list is staged
         long long spins = 0;
-        while (flag(slot) != i + 1) {
+        while (flag(k) != k + 1) {
             if (++spins > kPipeSpin || __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
                 if (lane == 0) pipe_give_up(P, fail);
                 return false;
@@ -385,80 +397,77 @@ __device__ __forceinline__ void pipe_resolve(const PipeParams &P, uint32_t *tk, 
         }
         return true;
     };
-    auto next = [&](int slot) { return slot + 1 == kRingL ? 0 : slot + 1; };
-    u64 kn = 0;  // keys of agent i + 1
-    if (!wait(0, 0)) return;
-    u64 kc = ring[0][lane];  // keys of agent i
-    uint32_t bc = word(kc);  // taken word of agent i's key, read before agent i - 1 chose
-    if (P.rows > 1) {
-        if (!wait(1, 1)) return;
-        kn = ring[1][lane];
+    const int R = P.rows;
+    uint32_t jn = 0xFFFFu;  // jobs of agent i + 1
+    if (!wait(0)) return;
+    uint32_t jc = jobs(0);   // jobs of agent i
+    uint32_t wc = word(jc);  // their taken words, read before agent i - 1 chose
+    if (R > 1) {
+        if (!wait(1)) return;
+        jn = jobs(1);
     }
-    int s2 = next(1);  // slot of agent i + 2
-    int jprev = -1;    // agent i - 1's job
-    for (int i = 0; i < P.rows; ++i) {
-        const uint32_t bn = word(kn);
-        u64 k2 = 0;
-        int f2 = 0;
-        if (i + 2 < P.rows) {
-            f2 = flag(s2);
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the key read stays after the flag read
-            k2 = ring[s2][lane];
-        }
-        const int jc = tkey_job(kc);
-        const bool fr = ((uint32_t)(kc >> 32) != 0u) & (((bc >> (jc & 31)) & 1u) == 0u) & (jc != jprev);
+    // agent k's job is published at the top of iteration k + 1 (and after the loop), so the
+    // LDS stores are not the last LDS accesses before the loop's wait for the next jobs.
+    // k = -1 publishes nothing: lane 0 ors 0 into its spare word and the pick word gets
+    // tag 0, which is never current (the agent's own word replaces it).
+    auto publish = [&](int k, int j) {
+        const bool real = k >= 0;
+        const int wd = real ? (j >> 5) : kTkWords;
+        const uint32_t bit = real ? 1u << (j & 31) : 0u;
+        // lane 0 sets the job's bit; the other lanes or 0 into their spare words
+        atomicOr(&tk[lane == 0 ? wd : kTkWords + lane], lane == 0 ? bit : 0u);
+        __hip_atomic_store(&P.picks[real ? k : 0], real ? ((uint32_t)(k + 1) << 16) | (uint32_t)j : 0u,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(P.progress, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // relaxed: agent k's jobs were consumed (used) before this store
+        __hip_atomic_store(&done[lane], k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    int jprev = -1;  // agent i - 1's job
+    for (int i = 0; i < R; ++i) {
+        publish(i - 1, jprev);  // before the taken-word reads of agent i + 1
+        const uint32_t wn = word(jn);
+        // agent i + 2's flag and jobs (slots past the last agent are read and ignored)
+        const int f2 = flag(i + 2);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the job read stays after the flag read
+        uint32_t j2 = jobs(i + 2);
+        const bool fr = (jc < (uint32_t)kPipeMaxN) & (((wc >> (jc & 31)) & 1u) == 0u) & ((int)jc != jprev);
         const unsigned long long m = __ballot(fr);
         if (m == 0) {  // cannot happen (a list never runs dry); never index with it
             if (lane == 0) pipe_give_up(P, fail);
             return;
         }
-        const int j = tkey_job(readlane64(kc, (int)__builtin_ctzll(m)));
-        if (lane == 0) {
-            atomicOr(&tk[j >> 5], 1u << (j & 31));  // no return value: no wait on the LDS
-            P.tau[i] = j;
-            P.sigma[j] = i;
-            __hip_atomic_store(&P.picks[i], ((uint32_t)(i + 1) << 16) | (uint32_t)j, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(P.progress, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // relaxed: agent i's keys were consumed (used) before this store
-            __hip_atomic_store(done, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        jprev = __builtin_amdgcn_readlane((int)jc, (int)__builtin_ctzll(m));
+        jc = jn;
+        wc = wn;
+        if (i + 2 < R && f2 != i + 3) {
+            if (!wait(i + 2)) return;
+            j2 = jobs(i + 2);
         }
-        jprev = j;
-        kc = kn;
-        bc = bn;
-        if (i + 2 < P.rows) {
-            if (f2 != i + 3) {
-                if (!wait(i + 2, s2)) return;
-                k2 = ring[s2][lane];
-            }
-            kn = k2;
-        }
-        s2 = next(s2);
+        jn = i + 2 < R ? j2 : 0xFFFFu;
     }
+    if (R > 0) publish(R - 1, jprev);
 }
 
 __global__ __launch_bounds__(kPipeT) void k_greedy_pipe(PipeParams P) {
-    __shared__ uint32_t tk[(kPipeMaxN + 31) / 32];  // taken jobs (producer: picks absorbed; resolver: all)
+    __shared__ uint32_t tk[kTkWords + 64];          // taken jobs (producer: picks absorbed; resolver: all)
     __shared__ u64 wl[kPW][64];
     __shared__ u64 cand[kPW][2 * 64];
-    __shared__ u64 ring[kRingL][64];                // resolver: one merged list per staged agent
+    __shared__ uint32_t ring[kRingL][64];           // resolver: the jobs of one merged list per staged agent
     __shared__ u64 stg[kPW - 1][kStage][64];        // resolver: a staging wave's part lists
     __shared__ int rdy[kRingL];
-    __shared__ int done, fail;
+    __shared__ int done[64], fail;  // done[0]: agents resolved (every lane writes its own word)
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int words = (P.n + 31) >> 5;
     for (int x = t; x < words; x += kPipeT) tk[x] = 0;
     if (t < kRingL) rdy[t] = 0;
-    if (t == 0) {
-        done = 0;
-        fail = 0;
-    }
+    if (t < 64) done[t] = 0;
+    if (t == 0) fail = 0;
     __syncthreads();
     auto give_up = [&]() { pipe_give_up(P, &fail); };
 
     if (blockIdx.x == 0) {  // ---- the resolver ----
         if (w == 0) {
-            pipe_resolve(P, tk, ring, rdy, &done, &fail, lane);
+            pipe_resolve(P, tk, ring, rdy, done, &fail, lane);
         } else {
             // waves 1..kPW-1 stage the lists of batches of A_per consecutive agents: load them
             // (A_per * Q <= kStage lists in flight per wave) as soon as they are produced, then
@@ -514,14 +523,14 @@ __global__ __launch_bounds__(kPipeT) void k_greedy_pipe(PipeParams P) {
                     }
                 }
                 spins = 0;
-                while (__hip_atomic_load(&done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= k0 + cnt - 1 - kRingL) {
+                while (__hip_atomic_load(&done[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= k0 + cnt - 1 - kRingL) {
                     if (++spins > kPipeSpin || __hip_atomic_load(&fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
                         if (lane == 0) give_up();
                         return;
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
-                for (int a = 0; a < cnt; ++a) ring[(k0 + a) % kRingL][lane] = sv[a][lane];
+                for (int a = 0; a < cnt; ++a) ring[(k0 + a) % kRingL][lane] = (uint32_t)tkey_job(sv[a][lane]);
                 if (lane == 0)
                     for (int k = k0; k < k0 + cnt; ++k)
                         // relaxed: this wave's LDS writes of the slot come first, in order
@@ -594,6 +603,15 @@ __global__ __launch_bounds__(kPipeT) void k_greedy_pipe(PipeParams P) {
         }
         __syncthreads();  // wl, cand and tk are reused by the next item
     }
+}
+
+// tau and sigma of the real agents from the pick words (after the persistent launch).
+__global__ __launch_bounds__(256) void k_picks_to_tau(const uint32_t *picks, int32_t *tau, int32_t *sigma, int rows) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= rows) return;
+    const int j = (int)(picks[i] & 0xFFFFu);
+    tau[i] = j;
+    sigma[j] = i;
 }
 
 // The virtual agents rows..n-1 of a rectangular instance take the jobs that
@@ -790,8 +808,6 @@ static bool launch_greedy_pipe(const int32_t *A, int32_t rows, int32_t n, int32_
     P.lists = (u64 *)scratch;
     P.picks = (uint32_t *)((char *)scratch + (size_t)kRingA * Q * kRound * sizeof(u64));
     P.progress = (int *)((char *)P.picks + (((size_t)rows * 4 + 255) & ~(size_t)255));  // within n * 4 + 512
-    P.tau = tau;
-    P.sigma = sigma;
     P.err = err;
     P.rows = rows;
     P.n = n;
@@ -807,7 +823,9 @@ static bool launch_greedy_pipe(const int32_t *A, int32_t rows, int32_t n, int32_
     const long long grid = 1 + (items < cap - 1 ? items : cap - 1);
     void *args[] = {&P};
     *e = hipLaunchCooperativeKernel((const void *)k_greedy_pipe, dim3((unsigned)grid), dim3(kPipeT), args, 0, s);
-    if (*e == hipSuccess) *e = launch_fill_virtual(tau, sigma, rows, n, s);
+    if (*e != hipSuccess) return true;
+    hipLaunchKernelGGL(k_picks_to_tau, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, P.picks, tau, sigma, rows);
+    if ((*e = hipGetLastError()) == hipSuccess) *e = launch_fill_virtual(tau, sigma, rows, n, s);
     return true;
 }
 
