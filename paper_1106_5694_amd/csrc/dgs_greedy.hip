@@ -337,7 +337,7 @@ constexpr int kStage = 8;  // lists in flight per staging wave
 struct PipeParams {
     const int32_t *A;   // rows x n
     u64 *lists;         // [kRingA][Q][kRound] tagged keys
-    uint32_t *picks;    // [rows] (agent + 1) << 16 | job; tau and sigma are written from them afterwards
+    uint32_t *picks;    // [-1 .. rows) (agent + 1) << 16 | job (picks[-1]: spare); tau and sigma are written from them
     int *progress;      // agents resolved so far; -1 once the resolver has given up
     int32_t *err;
     int rows, n, Q;
@@ -408,21 +408,19 @@ __device__ __forceinline__ void pipe_resolve(const PipeParams &P, uint32_t *tk, 
     }
     // agent k's job is published at the top of iteration k + 1 (and after the loop), so the
     // LDS stores are not the last LDS accesses before the loop's wait for the next jobs.
-    // k = -1 publishes nothing: lane 0 ors 0 into its spare word and the pick word gets
-    // tag 0, which is never current (the agent's own word replaces it).
+    // k = -1 publishes nothing: its job kPipeMaxN sets a bit in lane 0's spare word, and
+    // its pick word is the spare slot picks[-1].
     auto publish = [&](int k, int j) {
-        const bool real = k >= 0;
-        const int wd = real ? (j >> 5) : kTkWords;
-        const uint32_t bit = real ? 1u << (j & 31) : 0u;
         // lane 0 sets the job's bit; the other lanes or 0 into their spare words
-        atomicOr(&tk[lane == 0 ? wd : kTkWords + lane], lane == 0 ? bit : 0u);
-        __hip_atomic_store(&P.picks[real ? k : 0], real ? ((uint32_t)(k + 1) << 16) | (uint32_t)j : 0u,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicOr(&tk[lane == 0 ? (j >> 5) : kTkWords + lane], lane == 0 ? 1u << (j & 31) : 0u);
+        __hip_atomic_store(&P.picks[k], ((uint32_t)(k + 1) << 16) | (uint32_t)j, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(P.progress, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // relaxed: agent k's jobs were consumed (used) before this store
         __hip_atomic_store(&done[lane], k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
-    int jprev = -1;  // agent i - 1's job
+    static_assert(kPipeMaxN / 32 == kTkWords, "the first spare word holds job kPipeMaxN");
+    int jprev = kPipeMaxN;  // agent i - 1's job (none: no list holds it)
     for (int i = 0; i < R; ++i) {
         publish(i - 1, jprev);  // before the taken-word reads of agent i + 1
         const uint32_t wn = word(jn);
@@ -806,8 +804,9 @@ static bool launch_greedy_pipe(const int32_t *A, int32_t rows, int32_t n, int32_
     PipeParams P;
     P.A = A;
     P.lists = (u64 *)scratch;
-    P.picks = (uint32_t *)((char *)scratch + (size_t)kRingA * Q * kRound * sizeof(u64));
-    P.progress = (int *)((char *)P.picks + (((size_t)rows * 4 + 255) & ~(size_t)255));  // within n * 4 + 512
+    uint32_t *pick_words = (uint32_t *)((char *)scratch + (size_t)kRingA * Q * kRound * sizeof(u64));
+    P.picks = pick_words + 1;  // picks[-1] is the spare slot
+    P.progress = (int *)((char *)pick_words + (((size_t)rows * 4 + 4 + 255) & ~(size_t)255));  // within n * 4 + 512
     P.err = err;
     P.rows = rows;
     P.n = n;
@@ -817,7 +816,7 @@ static bool launch_greedy_pipe(const int32_t *A, int32_t rows, int32_t n, int32_
     if (P.A_per < 1) P.A_per = 1;
     // tags start at 1: cleared words never match
     if ((*e = launch_fill((int32_t *)P.lists, kRingA * Q * kRound * 2, 0, s)) != hipSuccess) return true;
-    if ((*e = launch_fill((int32_t *)P.picks, rows, 0, s)) != hipSuccess) return true;
+    if ((*e = launch_fill((int32_t *)pick_words, rows + 1, 0, s)) != hipSuccess) return true;
     if ((*e = launch_fill(P.progress, 1, 0, s)) != hipSuccess) return true;
     if (rows < n && (*e = launch_fill(sigma, n, -1, s)) != hipSuccess) return true;
     const long long grid = 1 + (items < cap - 1 ? items : cap - 1);
