@@ -337,7 +337,7 @@ constexpr int kStage = 8;  // lists in flight per staging wave
 struct PipeParams {
     const int32_t *A;   // rows x n
     u64 *lists;         // [kRingA][Q][kRound] tagged keys
-    uint32_t *picks;    // [-1 .. rows) (agent + 1) << 16 | job (picks[-1]: spare); tau and sigma are written from them
+    uint32_t *picks;    // [-2 .. rows) (agent + 1) << 16 | job (picks[-2], picks[-1]: spare); tau, sigma are written from them
     int *progress;      // agents resolved so far; -1 once the resolver has given up
     int32_t *err;
     int rows, n, Q;
@@ -363,21 +363,24 @@ __device__ __forceinline__ void pipe_give_up(const PipeParams &P, int *fail) {
 
 // The resolver wave: agents in order, each takes the first job of its staged list that
 // is free.  The list holds the jobs of the agent's best keys in decreasing key order
-// (0xFFFF: no key), so the first free job is the lowest free lane: one ballot.  The LDS
-// reads of agent i + 1's taken words and of agent i + 2's jobs go out before agent i
-// chooses, so no LDS round trip is on the per-agent path; the words of agent i + 1 then
-// miss only agent i's job, which the choice of agent i + 1 excludes by comparison.  The
-// jobs of agent i + 2 are read right after its ready flag, without waiting: this wave's
-// LDS accesses complete in order, so when the flag read sees the staged value the job
-// read sees the staged jobs (otherwise it is read again once the flag is set).  Every
-// lane runs the stores (the same value to one address, or to a lane's own spare word),
-// so the loop has no branch.  The words of agent i + 1 are read after agent i - 1's job
-// is published, so they miss only agent i's.
+// (0xFFFF: no key), so the first free job is the lowest free lane: one ballot.  Agents go
+// in pairs (a, a + 1) whose two chains run side by side: a + 1 takes its lowest free
+// lane unless that lane holds a's job, else its next free lane (a list's jobs are
+// distinct).  The LDS reads of the next pair's taken words and of the pair after it's
+// jobs go out before the current pair chooses, so no LDS round trip is on the per-pair
+// path.  The jobs are read right after their ready flags, without waiting: this wave's
+// LDS accesses complete in order, so when a flag read sees the staged value the job read
+// sees the staged jobs (otherwise it is read again once the flag is set).  A pair's
+// picks are published at the top of the next step, before the taken-word reads of the
+// pair after it, which then miss only the previous pair's two jobs (excluded by
+// comparison).  Every lane runs the stores (the same value to one address, or to a
+// lane's own spare word), so the loop has no branch.
 constexpr int kTkWords = (kPipeMaxN + 31) / 32;  // taken bitmap words; 64 spare words follow
 
 __device__ __forceinline__ void pipe_resolve(const PipeParams &P, uint32_t *tk, uint32_t (*ring)[64], int *rdy,
                                              int *done, int *fail, int lane) {
     static_assert((kRingL & (kRingL - 1)) == 0, "ring slots by mask");
+    static_assert(kPipeMaxN / 32 == kTkWords, "the first spare word holds job kPipeMaxN");
     auto word = [&](uint32_t j) { return tk[(j & (kPipeMaxN - 1)) >> 5]; };
     auto flag = [&](int k) {
         return __hip_atomic_load(&rdy[k & (kRingL - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -397,53 +400,80 @@ __device__ __forceinline__ void pipe_resolve(const PipeParams &P, uint32_t *tk, 
         }
         return true;
     };
-    const int R = P.rows;
-    uint32_t jn = 0xFFFFu;  // jobs of agent i + 1
-    if (!wait(0)) return;
-    uint32_t jc = jobs(0);   // jobs of agent i
-    uint32_t wc = word(jc);  // their taken words, read before agent i - 1 chose
-    if (R > 1) {
-        if (!wait(1)) return;
-        jn = jobs(1);
-    }
-    // agent k's job is published at the top of iteration k + 1 (and after the loop), so the
-    // LDS stores are not the last LDS accesses before the loop's wait for the next jobs.
-    // k = -1 publishes nothing: its job kPipeMaxN sets a bit in lane 0's spare word, and
-    // its pick word is the spare slot picks[-1].
+    // agent k's job is published at the top of the next step (and after the loop).  k < 0
+    // publishes nothing: its job kPipeMaxN sets a bit in lane 0's spare word, and its pick
+    // word is one of the spare slots picks[-2], picks[-1].
     auto publish = [&](int k, int j) {
         // lane 0 sets the job's bit; the other lanes or 0 into their spare words
         atomicOr(&tk[lane == 0 ? (j >> 5) : kTkWords + lane], lane == 0 ? 1u << (j & 31) : 0u);
         __hip_atomic_store(&P.picks[k], ((uint32_t)(k + 1) << 16) | (uint32_t)j, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(P.progress, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // relaxed: agent k's jobs were consumed (used) before this store
-        __hip_atomic_store(&done[lane], k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
-    static_assert(kPipeMaxN / 32 == kTkWords, "the first spare word holds job kPipeMaxN");
-    int jprev = kPipeMaxN;  // agent i - 1's job (none: no list holds it)
-    for (int i = 0; i < R; ++i) {
-        publish(i - 1, jprev);  // before the taken-word reads of agent i + 1
-        const uint32_t wn = word(jn);
-        // agent i + 2's flag and jobs (slots past the last agent are read and ignored)
-        const int f2 = flag(i + 2);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the job read stays after the flag read
-        uint32_t j2 = jobs(i + 2);
-        const bool fr = (jc < (uint32_t)kPipeMaxN) & (((wc >> (jc & 31)) & 1u) == 0u) & ((int)jc != jprev);
-        const unsigned long long m = __ballot(fr);
-        if (m == 0) {  // cannot happen (a list never runs dry); never index with it
+    auto progress = [&](int nd) {
+        __hip_atomic_store(P.progress, nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // relaxed: the published agents' jobs were consumed (used) before this store
+        __hip_atomic_store(&done[lane], nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    const int R = P.rows;
+    uint32_t jr[4];  // jobs of agents 0..3 (0xFFFF past the last agent)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        jr[k] = 0xFFFFu;
+        if (k < R) {
+            if (!wait(k)) return;
+            jr[k] = jobs(k);
+        }
+    }
+    uint32_t ja = jr[0], jb = jr[1], jna = jr[2], jnb = jr[3];  // the pair, the next pair
+    uint32_t wa = word(ja), wb = word(jb);  // their taken words, missing the previous pair's jobs
+    int j2 = kPipeMaxN, j1 = kPipeMaxN;      // the previous pair's jobs (none: no list holds them)
+    for (int a = 0; a < R; a += 2) {
+        publish(a - 2, j2);
+        publish(a - 1, j1);
+        progress(a);
+        const uint32_t wna = word(jna), wnb = word(jnb);
+        const int f4 = flag(a + 4), f5 = flag(a + 5);  // (slots past the last agent: ignored)
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);      // the job reads stay after the flag reads
+        uint32_t j4 = jobs(a + 4), j5 = jobs(a + 5);
+        auto is_free = [&](uint32_t j, uint32_t w) {
+            return (j < (uint32_t)kPipeMaxN) & (((w >> (j & 31)) & 1u) == 0u) & ((int)j != j2) & ((int)j != j1);
+        };
+        const unsigned long long ma = __ballot(is_free(ja, wa));
+        const unsigned long long mb = __ballot(is_free(jb, wb));
+        const unsigned long long mb2 = mb & (mb - 1);  // without its lowest lane
+        const int pa = __builtin_amdgcn_readlane((int)ja, (int)__builtin_ctzll(ma | (1ull << 63)));
+        const int pb1 = __builtin_amdgcn_readlane((int)jb, (int)__builtin_ctzll(mb | (1ull << 63)));
+        const int pb2 = __builtin_amdgcn_readlane((int)jb, (int)__builtin_ctzll(mb2 | (1ull << 63)));
+        const bool b_real = a + 1 < R;
+        const bool ok_b = mb2 != 0 || (mb != 0 && pb1 != pa);
+        if (ma == 0 || (b_real && !ok_b)) {  // cannot happen (a list never runs dry); never index with it
             if (lane == 0) pipe_give_up(P, fail);
             return;
         }
-        jprev = __builtin_amdgcn_readlane((int)jc, (int)__builtin_ctzll(m));
-        jc = jn;
-        wc = wn;
-        if (i + 2 < R && f2 != i + 3) {
-            if (!wait(i + 2)) return;
-            j2 = jobs(i + 2);
+        j2 = pa;
+        j1 = b_real ? (pb1 != pa ? pb1 : pb2) : kPipeMaxN;
+        ja = jna;
+        jb = jnb;
+        wa = wna;
+        wb = wnb;
+        if (a + 4 < R && f4 != a + 5) {
+            if (!wait(a + 4)) return;
+            j4 = jobs(a + 4);
         }
-        jn = i + 2 < R ? j2 : 0xFFFFu;
+        if (a + 5 < R && f5 != a + 6) {
+            if (!wait(a + 5)) return;
+            j5 = jobs(a + 5);
+        }
+        jna = a + 4 < R ? j4 : 0xFFFFu;
+        jnb = a + 5 < R ? j5 : 0xFFFFu;
     }
-    if (R > 0) publish(R - 1, jprev);
+    // the last pair (its second agent only when it exists)
+    const int last = (R - 1) & ~1;
+    if (R > 0) {
+        publish(last, j2);
+        publish(last + 1 < R ? last + 1 : -1, j1);
+        progress(R);
+    }
 }
 
 __global__ __launch_bounds__(kPipeT) void k_greedy_pipe(PipeParams P) {
@@ -805,8 +835,8 @@ static bool launch_greedy_pipe(const int32_t *A, int32_t rows, int32_t n, int32_
     P.A = A;
     P.lists = (u64 *)scratch;
     uint32_t *pick_words = (uint32_t *)((char *)scratch + (size_t)kRingA * Q * kRound * sizeof(u64));
-    P.picks = pick_words + 1;  // picks[-1] is the spare slot
-    P.progress = (int *)((char *)pick_words + (((size_t)rows * 4 + 4 + 255) & ~(size_t)255));  // within n * 4 + 512
+    P.picks = pick_words + 2;  // picks[-2], picks[-1] are spare slots
+    P.progress = (int *)((char *)pick_words + (((size_t)rows * 4 + 8 + 255) & ~(size_t)255));  // within n * 4 + 512
     P.err = err;
     P.rows = rows;
     P.n = n;
@@ -816,7 +846,7 @@ static bool launch_greedy_pipe(const int32_t *A, int32_t rows, int32_t n, int32_
     if (P.A_per < 1) P.A_per = 1;
     // tags start at 1: cleared words never match
     if ((*e = launch_fill((int32_t *)P.lists, kRingA * Q * kRound * 2, 0, s)) != hipSuccess) return true;
-    if ((*e = launch_fill((int32_t *)pick_words, rows + 1, 0, s)) != hipSuccess) return true;
+    if ((*e = launch_fill((int32_t *)pick_words, rows + 2, 0, s)) != hipSuccess) return true;
     if ((*e = launch_fill(P.progress, 1, 0, s)) != hipSuccess) return true;
     if (rows < n && (*e = launch_fill(sigma, n, -1, s)) != hipSuccess) return true;
     const long long grid = 1 + (items < cap - 1 ? items : cap - 1);
