@@ -597,3 +597,18 @@ def test_rect_from_global_greedy_worked_example():
     assert list(r["tau"]) == [0, 1] and r["f"] == 15 and r["S"] == 0
     s = oracle.rect_dgs_full(np.array(GG_A, dtype=np.int32))
     assert list(s["tau"]) == [1, 2] and s["f"] == 12 and s["S"] == 0
+
+
+def test_is_permutation_definition():
+    """orc_is_permutation against the definition (the values are exactly
+    0..n-1, each once) on hand-picked non-permutations -- a repeated value, a
+    value n, a negative value, all equal -- and on random arrays, half of them
+    permutations."""
+    assert oracle.is_permutation([0]) and oracle.is_permutation([2, 0, 1])
+    for bad in ([1], [-1], [0, 0], [1, 1], [0, 2], [3, 0, 1], [0, 1, -1], [2, 2, 2], [1, 2, 3]):
+        assert not oracle.is_permutation(bad), bad
+    rng = np.random.default_rng(11)
+    for trial in range(200):
+        n = int(rng.integers(1, 40))
+        t = rng.permutation(n) if trial % 2 else rng.integers(-2, n + 2, size=n)
+        assert oracle.is_permutation(t) == (sorted(int(x) for x in t) == list(range(n)))
