@@ -663,6 +663,7 @@ dgs_status run_batch(const BatchCall &c) {
         int32_t *h_order = (int32_t *)(arena.host + items_b);
         int64_t *h_res = (int64_t *)(arena.host + items_b + order_b);
         size_t om = 0, ov = 0, ol = 0;
+        int64_t tiles = 0;
         for (size_t x = 0; x < m; ++x) {
             const int32_t b = small[x];
             const int32_t n = c.ns[b];
@@ -680,7 +681,8 @@ dgs_status run_batch(const BatchCall &c) {
             it.lists = (u64 *)(lst + ol);
             it.res = d_res + 5 * x;
             it.n = n;
-            it.pad = 0;
+            it.tile0 = (int)tiles;
+            tiles += batch_tiles(n);
             om += al((size_t)n * n * 4);
             ol += al((size_t)n * 16);
             h_order[x] = (int32_t)x;
@@ -696,7 +698,7 @@ dgs_status run_batch(const BatchCall &c) {
         int grid = (int)std::min<size_t>(m, (size_t)limit);
         if (c.grid_cap > 0) grid = std::min(grid, c.grid_cap);
         DGS_HIP(hipEventRecord(arena.ev0, s));
-        DGS_HIP(launch_batch(d_items, d_order, (int)m, d_queue, c.max_switches, g_batch_block, grid, s));
+        DGS_HIP(launch_batch(d_items, d_order, (int)m, d_queue, c.max_switches, tiles, g_batch_block, grid, s));
         DGS_HIP(hipEventRecord(arena.ev1, s));
         DGS_HIP(hipMemcpyAsync(h_res, d_res, m * 5 * 8, hipMemcpyDeviceToHost, s));
         DGS_HIP(hipStreamSynchronize(s));

@@ -6,7 +6,9 @@
 //      in order; thread t owns columns t, t + BLOCK, ...; one block max per
 //      agent over the free columns (each thread tracks its own columns'
 //      taken flags in registers);
-//   2. transpose AT = A^T through LDS tiles;
+//   2. AT = A^T, for every instance at once before the persistent launch
+//      (k_batch_transpose over the whole device: the largest instances' own
+//      workgroups would otherwise spend milliseconds on it);
 //   3. difference evaluation of every agent (Algorithm 2): a wave stages row
 //      r of A in LDS and scores g(r, c) = a[r][tau(c)] + AT[tau(r)][c]
 //      - d(r) - d(c) for all c; each agent starts with its best exchange and
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
     __shared__ uint16_t rt[kBatchMaxN];
     __shared__ uint16_t rs[kBatchMaxN];
     __shared__ int32_t rd[kBatchMaxN];
-    __shared__ int32_t rowbuf[NW][kBatchMaxN + 64];  // per-wave staged rows / 32 x 65 transpose tiles
+    __shared__ int32_t rowbuf[NW][kBatchMaxN + 64];  // per-wave staged rows
     __shared__ u64 red[4 * NW];
     __shared__ int s_item;
     __shared__ int dirty_list[kBatchMaxN];
@@ -241,35 +243,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
             continue;
         }
 
-        // ---- 2. transpose A -> AT through 64x64 LDS tiles (one tile per wave) ---------------
-        {
-            int32_t *tile = rowbuf[w];  // 32 x 65 ints
-            const int nt = (n + 63) / 64;
-            for (int tt = w; tt < nt * nt; tt += NW) {
-                const int bi = tt / nt, bj = tt % nt;
-                // two passes of 32 rows (a 64 x 32 tile with padding fits the wave's buffer)
-                for (int h = 0; h < 2; ++h) {
-                    int v[32];  // the 32 rows' loads all in flight at once
-#pragma unroll
-                    for (int rr = 0; rr < 32; ++rr) {
-                        const int row = bi * 64 + h * 32 + rr, col = bj * 64 + lane;
-                        v[rr] = (row < n && col < n) ? A[(int64_t)row * n + col] : 0;
-                    }
-#pragma unroll
-                    for (int rr = 0; rr < 32; ++rr) tile[rr * 65 + lane] = v[rr];
-                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                    // AT[col][row] for col = bj*64 + cc, row = bi*64 + h*32 + lane (lane < 32)
-#pragma unroll 8
-                    for (int cc = 0; cc < 64; ++cc) {
-                        const int col = bj * 64 + cc, row = bi * 64 + h * 32 + lane;
-                        if (lane < 32 && col < n && row < n) I.AT[(int64_t)col * n + row] = tile[lane * 65 + cc];
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                }
-            }
-        }
-        __syncthreads();
-        __threadfence_block();
+        // ---- 2. AT = A^T: written by k_batch_transpose before this launch -------------------
 
         // ---- 3. difference evaluation of every agent -------------------------------------------
         // wave w evaluates agents w, w + NW, ...; results go to the agents' owner
@@ -421,10 +395,60 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
     }
 }
 
+// AT = A^T of every instance in 64 x 64 tiles over the whole device.  Global tile g
+// belongs to the last item x (in table order) with items[x].tile0 <= g.
+__global__ __launch_bounds__(256) void k_batch_transpose(const BatchItem *items, int count, int64_t tiles) {
+    __shared__ int32_t tile[64][65];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int64_t g = blockIdx.x; g < tiles; g += gridDim.x) {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].tile0 <= g)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int32_t *A = items[lo].A;
+        int32_t *AT = items[lo].AT;
+        const int n = items[lo].n, nt = (n + 63) >> 6;
+        const int local = (int)(g - items[lo].tile0), bi = local / nt, bj = local % nt;
+        int v[16];  // wave w: rows w, w + 4, ..., all 16 loads in flight
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int row = bi * 64 + w + 4 * k, col = bj * 64 + lane;
+            v[k] = (row < n && col < n) ? A[(int64_t)row * n + col] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tile[w + 4 * k][lane] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int col = bj * 64 + w + 4 * k, row = bi * 64 + lane;
+            if (col < n && row < n) AT[(int64_t)col * n + row] = tile[lane][w + 4 * k];
+        }
+        __syncthreads();  // the tile is rewritten next
+    }
+}
+
 }  // namespace
 
 hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
-                        int64_t max_switches, int block, int grid, hipStream_t s) {
+                        int64_t max_switches, int64_t tiles, int block, int grid, hipStream_t s) {
+    if (tiles > 0) {
+        static int cap = -1;
+        if (cap < 0) {
+            int dev = 0, cus = 0, per = 0;
+            cap = 1024;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_transpose, 256, 0) == hipSuccess &&
+                cus * per > 0)
+                cap = cus * per;
+        }
+        hipLaunchKernelGGL(k_batch_transpose, dim3((unsigned)(tiles < cap ? tiles : cap)), dim3(256), 0, s, items,
+                           count, tiles);
+    }
     if (block == 512) {
         hipLaunchKernelGGL(k_batch_solve<512>, dim3((unsigned)grid), dim3(512), 0, s, items, order, count, queue,
                            max_switches);

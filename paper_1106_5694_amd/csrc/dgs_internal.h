@@ -159,10 +159,17 @@ struct BatchItem {
     u64 *lists;        // 2n scratch
     int64_t *res;      // [0] f0 [1] f [2] switches [3] re-evaluations [4] status
     int n;
-    int pad;
+    int tile0;  // first of the instance's ceil(n/64)^2 transpose tiles (running count in table order)
 };
+// The batched solve: every instance's transpose over the whole device (tiles = the total
+// count of 64 x 64 tiles), then the persistent solver.
 hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
-                        int64_t max_switches, int block, int grid, hipStream_t s);
+                        int64_t max_switches, int64_t tiles, int block, int grid, hipStream_t s);
+// Transpose tiles of an instance of size n.
+inline int64_t batch_tiles(int n) {
+    const int64_t nt = (n + 63) / 64;
+    return nt * nt;
+}
 int batch_grid_limit(int block);
 
 // Parallel DGS (dgs_parallel.hip): one round of Check Conflicts over the

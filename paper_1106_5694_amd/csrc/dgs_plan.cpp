@@ -97,6 +97,7 @@ struct dgs_batch_plan {
     char *dev = nullptr;
     std::vector<int32_t *> A, tau;  // per instance
     dgs::BatchItem *d_items = nullptr;
+    int64_t tiles = 0;  // transpose tiles of all instances
     int32_t *d_order = nullptr;
     int64_t *d_res = nullptr;  // 5 per launch slot
     int32_t *d_queue = nullptr;
@@ -158,7 +159,8 @@ dgs_status run_eager(dgs_batch_plan *p, int block, float *ms) {
     hipStream_t s = p->stream;
     DGS_HIP(dgs::launch_fill(p->d_queue, 1, 0, s));
     DGS_HIP(hipEventRecord(p->ev0, s));
-    DGS_HIP(dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, block, grid, s));
+    DGS_HIP(dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, p->tiles, block, grid,
+                              s));
     DGS_HIP(hipEventRecord(p->ev1, s));
     DGS_HIP(hipMemcpyAsync(p->h_res, p->d_res, (size_t)p->count * 5 * 8, hipMemcpyDeviceToHost, s));
     DGS_HIP(hipStreamSynchronize(s));
@@ -171,7 +173,8 @@ dgs_status capture(dgs_batch_plan *p) {
     DGS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = dgs::launch_fill(p->d_queue, 1, 0, s);
     if (e == hipSuccess)
-        e = dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, p->block, p->grid, s);
+        e = dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, p->tiles, p->block,
+                              p->grid, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->h_res, p->d_res, (size_t)p->count * 5 * 8, hipMemcpyDeviceToHost, s);
     hipGraph_t g = nullptr;
@@ -310,7 +313,8 @@ dgs_status dgs_batch_plan_create(int32_t count, const int32_t *ns, const dgs_opt
         it.lists = (dgs::u64 *)(l_base + ol);
         it.res = p->d_res + 5 * x;
         it.n = n;
-        it.pad = 0;
+        it.tile0 = (int)p->tiles;
+        p->tiles += dgs::batch_tiles(n);
         order[x] = x;
         om += dgs::al256((size_t)n * n * 4);
         ol += dgs::al256((size_t)n * 16);
