@@ -618,10 +618,12 @@ dgs_status run_batch(const BatchCall &c) {
             mat += al((size_t)c.ns[b] * c.ns[b] * 4);
             vec += al((size_t)c.ns[b] * 4);
         }
-        size_t lists = 0;
+        size_t lists = 0, parts = 0;
         for (int32_t b : small) lists += al((size_t)c.ns[b] * 16);
+        for (int32_t b : small) parts += al(batch_part_bytes(c.ns[b]));
         const size_t items_b = al(m * sizeof(BatchItem)), order_b = al(m * 4), res_b = al(m * 5 * 8);
-        const size_t dev_bytes = (c.dev ? 0 : mat) + mat + lists + (c.dev ? 0 : vec) + items_b + order_b + res_b + 256;
+        const size_t dev_bytes =
+            (c.dev ? 0 : mat) + mat + lists + parts + (c.dev ? 0 : vec) + items_b + order_b + res_b + 256;
         const size_t host_bytes = items_b + order_b + res_b;
         dgs_status st = batch_reserve(arena, dev_bytes, host_bytes, !c.pool);
         if (st != DGS_OK) return st;
@@ -648,6 +650,8 @@ dgs_status run_batch(const BatchCall &c) {
         p += mat;
         char *lst = p;
         p += lists;
+        char *prt = p;
+        p += parts;
         if (!c.dev) {
             tauo = p;
             p += vec;
@@ -662,8 +666,8 @@ dgs_status run_batch(const BatchCall &c) {
         BatchItem *h_items = (BatchItem *)arena.host;
         int32_t *h_order = (int32_t *)(arena.host + items_b);
         int64_t *h_res = (int64_t *)(arena.host + items_b + order_b);
-        size_t om = 0, ov = 0, ol = 0;
-        int64_t tiles = 0;
+        size_t om = 0, ov = 0, ol = 0, op = 0;
+        BatchTotals tot;
         for (size_t x = 0; x < m; ++x) {
             const int32_t b = small[x];
             const int32_t n = c.ns[b];
@@ -681,15 +685,16 @@ dgs_status run_batch(const BatchCall &c) {
             it.lists = (u64 *)(lst + ol);
             it.res = d_res + 5 * x;
             it.n = n;
-            it.tile0 = (int)tiles;
-            tiles += batch_tiles(n);
+            it.part = (u64 *)(prt + op);
+            op += al(batch_part_bytes(n));
+            batch_place(it, tot);
             om += al((size_t)n * n * 4);
             ol += al((size_t)n * 16);
             h_order[x] = (int32_t)x;
         }
         DGS_HIP(hipMemcpyAsync(d_items, h_items, m * sizeof(BatchItem), hipMemcpyHostToDevice, s));
         DGS_HIP(hipMemcpyAsync(d_order, h_order, m * 4, hipMemcpyHostToDevice, s));
-        DGS_HIP(launch_fill(d_queue, 1, 0, s));
+        DGS_HIP(launch_fill(d_queue, 2, 0, s));
         const int limit = batch_grid_limit(g_batch_block);
         if (limit < 1) {
             set_error("cannot size the batched solver's grid");
@@ -698,7 +703,7 @@ dgs_status run_batch(const BatchCall &c) {
         int grid = (int)std::min<size_t>(m, (size_t)limit);
         if (c.grid_cap > 0) grid = std::min(grid, c.grid_cap);
         DGS_HIP(hipEventRecord(arena.ev0, s));
-        DGS_HIP(launch_batch(d_items, d_order, (int)m, d_queue, c.max_switches, tiles, g_batch_block, grid, s));
+        DGS_HIP(launch_batch(d_items, d_order, (int)m, d_queue, c.max_switches, tot, g_batch_block, grid, s));
         DGS_HIP(hipEventRecord(arena.ev1, s));
         DGS_HIP(hipMemcpyAsync(h_res, d_res, m * 5 * 8, hipMemcpyDeviceToHost, s));
         DGS_HIP(hipStreamSynchronize(s));

@@ -1,7 +1,8 @@
-// Batched DGS on gfx950: many independent instances (n <= kBatchMaxN) in one
-// persistent launch.  Workgroups take instances from a device-side queue
-// (largest first) and solve each one alone, end to end, so no data crosses
-// workgroups:
+// Batched DGS on gfx950: many independent instances (n <= kBatchMaxN).  The
+// greedy starts and the switching run in persistent launches whose workgroups
+// take instances from a device-side queue (largest first) and work on each one
+// alone; the transposes and the difference evaluations of all instances are
+// spread over the whole device between them:
 //   1. greedy start (Section 3.1) with the value-range check fused in: agents
 //      in order; thread t owns columns t, t + BLOCK, ...; one block max per
 //      agent over the free columns (each thread tracks its own columns'
@@ -9,9 +10,9 @@
 //   2. AT = A^T, for every instance at once before the persistent launch
 //      (k_batch_transpose over the whole device: the largest instances' own
 //      workgroups would otherwise spend milliseconds on it);
-//   3. difference evaluation of every agent (Algorithm 2): a wave stages row
-//      r of A in LDS and scores g(r, c) = a[r][tau(c)] + AT[tau(r)][c]
-//      - d(r) - d(c) for all c; each agent starts with its best exchange and
+//   3. difference evaluation of every agent (Algorithm 2), for every instance
+//      at once: k_batch_pairs scores the tile pairs of all instances (each
+//      entry read once), k_batch_reduce keeps each agent's best exchange and
 //      the second best as its bound;
 //   4. switching (Algorithm 1 as steepest ascent): block max over the
 //      agents' list maxima, apply, update every agent's two changed
@@ -148,7 +149,10 @@ __device__ __forceinline__ void wave_eval_row(const int32_t *A, const int32_t *A
     wave_top2(b1, b2);
 }
 
-template <int BLOCK>
+// PHASE 0: the greedy start with the range check (tau and res[0], res[4] out); PHASE 1:
+// the switching from the evaluation's lists (k_batch_pairs, k_batch_reduce between the
+// two launches).  Each phase takes the instances from its own queue word, largest first.
+template <int BLOCK, int PHASE>
 __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, const int32_t *order, int count,
                                                         int32_t *queue, int64_t max_switches) {
     constexpr int RPT = kBatchMaxN / BLOCK;  // agents (and columns) per thread
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
     int slot = 0;
 
     for (;;) {
-        if (t == 0) s_item = atomicAdd(queue, 1);
+        if (t == 0) s_item = atomicAdd(&queue[PHASE], 1);
         __syncthreads();
         const int it = s_item;
         __syncthreads();
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
         const BatchItem I = items[order[it]];
         const int n = I.n;
         const int32_t *A = I.A;
-
+        if constexpr (PHASE == 0) {
         // ---- 1. greedy start + range check -----------------------------------------------
         bool taken[RPT];
 #pragma unroll
@@ -243,19 +247,28 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
             continue;
         }
 
-        // ---- 2. AT = A^T: written by k_batch_transpose before this launch -------------------
-
-        // ---- 3. difference evaluation of every agent -------------------------------------------
-        // wave w evaluates agents w, w + NW, ...; results go to the agents' owner
-        // threads through I.lists (private to this workgroup).
-        for (int r = w; r < n; r += NW) {
-            u64 b1, b2;
-            wave_eval_row(A, I.AT, n, r, rt, rd, rowbuf[w], b1, b2);
-            if (lane == 0) {
-                I.lists[2 * r] = b1;
-                I.lists[2 * r + 1] = b2;
-            }
+        for (int r = t; r < n; r += BLOCK) I.tau[r] = rt[r];
+        if (t == 0) {
+            I.res[0] = f0;
+            I.res[4] = DGS_OK;
         }
+        __syncthreads();
+        continue;
+        } else {
+        // (AT = A^T was written by k_batch_transpose, the evaluation's lists by
+        // k_batch_pairs and k_batch_reduce)
+        if (I.res[4] != DGS_OK) {  // the range check failed (same in every thread)
+            __syncthreads();
+            continue;
+        }
+        // the greedy start: tau, sigma and the benefits d
+        for (int r = t; r < n; r += BLOCK) {
+            const int j = I.tau[r];
+            rt[r] = (uint16_t)j;
+            rs[j] = (uint16_t)r;
+            rd[r] = A[(int64_t)r * n + j];
+        }
+        const int64_t f0 = I.res[0];
         __syncthreads();
         u64 L[RPT][kBM];
         u64 B[RPT];
@@ -392,6 +405,148 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
             I.res[4] = DGS_OK;
         }
         __syncthreads();
+        }
+    }
+}
+
+// The difference evaluation of every instance over the whole device: workgroup g scores
+// tile pair g of the batch (the last item x, in table order, with items[x].pair0 <= g;
+// an item whose range check failed is skipped).  Tile pair (I, K), I <= K, of an
+// instance: g(i, k) = a[i][tau(k)] + a[k][tau(i)] - d(i) - d(k) for i in block I, k in
+// block K, both tiles read from A^T through tau (row tau(x) of A^T holds a[.][tau(x)]);
+// per (agent, partner block) the top-2 keys (gain, job) into the instance's partials.
+__global__ __launch_bounds__(512) void k_batch_pairs(const BatchItem *items, int count) {
+    constexpr int BLOCK = 512, Q = BLOCK / 64, E = 64 / Q, LD = (64 * 64 / 4) / BLOCK;
+    __shared__ int32_t tA[64][65];
+    __shared__ int32_t tB[64][65];
+    __shared__ int32_t dI[64], dK[64], jI[64], jK[64];
+    const int64_t g = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].pair0 <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    if (items[lo].res[4] != DGS_OK) return;
+    const int32_t *A = items[lo].A, *AT = items[lo].AT, *tau = items[lo].tau;
+    u64 *part = items[lo].part;
+    const int n = items[lo].n, nb = (n + 63) >> 6;
+    int bI, bK;
+    pair_of(g - items[lo].pair0, nb, bI, bK);
+    const int i0 = bI * 64, k0 = bK * 64, t = threadIdx.x;
+    auto row = [&](int x) { return AT + (int64_t)tau[x] * n; };
+    if ((n % 4 == 0) && i0 + 64 <= n && k0 + 64 <= n) {
+        int4 va[LD], vb[LD];
+#pragma unroll
+        for (int u = 0; u < LD; ++u) {
+            const int e = t + u * BLOCK;
+            const int r = e >> 4, c4 = (e & 15) * 4;
+            va[u] = *(const int4 *)(row(i0 + r) + k0 + c4);
+            vb[u] = *(const int4 *)(row(k0 + r) + i0 + c4);
+        }
+#pragma unroll
+        for (int u = 0; u < LD; ++u) {
+            const int e = t + u * BLOCK;
+            const int r = e >> 4, c4 = (e & 15) * 4;
+            tA[r][c4] = va[u].x;
+            tA[r][c4 + 1] = va[u].y;
+            tA[r][c4 + 2] = va[u].z;
+            tA[r][c4 + 3] = va[u].w;
+            tB[r][c4] = vb[u].x;
+            tB[r][c4 + 1] = vb[u].y;
+            tB[r][c4 + 2] = vb[u].z;
+            tB[r][c4 + 3] = vb[u].w;
+        }
+    } else {
+        for (int e = t; e < 64 * 64; e += BLOCK) {
+            const int r = e >> 6, c = e & 63;
+            tA[r][c] = (i0 + r < n && k0 + c < n) ? row(i0 + r)[k0 + c] : 0;
+            tB[r][c] = (k0 + r < n && i0 + c < n) ? row(k0 + r)[i0 + c] : 0;
+        }
+    }
+    if (t < 64) {
+        const int x = i0 + t;
+        jI[t] = x < n ? tau[x] : 0;
+        dI[t] = x < n ? A[(int64_t)x * n + tau[x]] : 0;
+    } else if (t < 128) {
+        const int x = k0 + t - 64;
+        jK[t - 64] = x < n ? tau[x] : 0;
+        dK[t - 64] = x < n ? A[(int64_t)x * n + tau[x]] : 0;
+    }
+    __syncthreads();
+    const int rt = t / Q, q = t % Q;
+    u64 a1 = 0, a2 = 0, c1 = 0, c2 = 0;  // row rt of I against K; row rt of K against I
+    if (bI != bK && i0 + 64 <= n && k0 + 64 <= n) {
+        const int di = dI[rt], dk = dK[rt];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int c = q * E + e;
+            top2_push(a1, a2, mk_key((tA[rt][c] + tB[c][rt]) - (di + dK[c]), jK[c]));
+            top2_push(c1, c2, mk_key((tA[c][rt] + tB[rt][c]) - (dI[c] + dk), jI[c]));
+        }
+    } else {
+        if (i0 + rt < n) {
+            const int di = dI[rt];
+            for (int e = 0; e < E; ++e) {
+                const int k = q * E + e;
+                if (k0 + k >= n || (bI == bK && k == rt)) continue;
+                top2_push(a1, a2, mk_key((tA[rt][k] + tB[k][rt]) - (di + dK[k]), jK[k]));
+            }
+        }
+        if (bI != bK && k0 + rt < n) {
+            const int dk = dK[rt];
+            for (int e = 0; e < E; ++e) {
+                const int i = q * E + e;
+                if (i0 + i >= n) continue;
+                top2_push(c1, c2, mk_key((tA[i][rt] + tB[rt][i]) - (dI[i] + dk), jI[i]));
+            }
+        }
+    }
+    // merge the Q threads of each row (adjacent lanes; lane distances as template arguments)
+    static_assert(Q == 8, "three merge steps");
+    top2_merge(a1, a2, xor_lanes64<1>(a1), xor_lanes64<1>(a2));
+    top2_merge(c1, c2, xor_lanes64<1>(c1), xor_lanes64<1>(c2));
+    top2_merge(a1, a2, xor_lanes64<2>(a1), xor_lanes64<2>(a2));
+    top2_merge(c1, c2, xor_lanes64<2>(c1), xor_lanes64<2>(c2));
+    top2_merge(a1, a2, xor_lanes64<4>(a1), xor_lanes64<4>(a2));
+    top2_merge(c1, c2, xor_lanes64<4>(c1), xor_lanes64<4>(c2));
+    if (q == 0 && i0 + rt < n) {
+        u64 *o = part + ((size_t)(i0 + rt) * nb + bK) * 2;
+        o[0] = a1;
+        o[1] = a2;
+    }
+    if (q == 0 && bI != bK && k0 + rt < n) {
+        u64 *o = part + ((size_t)(k0 + rt) * nb + bI) * 2;
+        o[0] = c1;
+        o[1] = c2;
+    }
+}
+
+// One wave per agent of the batch (the last item x with items[x].agent0 <= agent): the
+// top-2 of its block partials into the instance's lists (best, then the bound).
+__global__ __launch_bounds__(256) void k_batch_reduce(const BatchItem *items, int count, int64_t agents) {
+    const int64_t a = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (a >= agents) return;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].agent0 <= a)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    if (items[lo].res[4] != DGS_OK) return;
+    const int n = items[lo].n, nb = (n + 63) >> 6, r = (int)(a - items[lo].agent0);
+    const u64 *p = items[lo].part + (size_t)r * nb * 2;
+    u64 b1 = 0, b2 = 0;
+    for (int x = lane; x < nb; x += 64) top2_merge(b1, b2, p[2 * x], p[2 * x + 1]);
+    wave_top2(b1, b2);
+    if (lane == 0) {
+        items[lo].lists[2 * r] = b1;
+        items[lo].lists[2 * r + 1] = b2;
     }
 }
 
@@ -434,28 +589,35 @@ __global__ __launch_bounds__(256) void k_batch_transpose(const BatchItem *items,
 }  // namespace
 
 hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
-                        int64_t max_switches, int64_t tiles, int block, int grid, hipStream_t s) {
-    if (tiles > 0) {
-        static int cap = -1;
-        if (cap < 0) {
-            int dev = 0, cus = 0, per = 0;
-            cap = 1024;
-            if (hipGetDevice(&dev) == hipSuccess &&
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_transpose, 256, 0) == hipSuccess &&
-                cus * per > 0)
-                cap = cus * per;
-        }
-        hipLaunchKernelGGL(k_batch_transpose, dim3((unsigned)(tiles < cap ? tiles : cap)), dim3(256), 0, s, items,
-                           count, tiles);
+                        int64_t max_switches, const BatchTotals &tot, int block, int grid, hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    static int cap = -1;
+    if (cap < 0) {
+        int dev = 0, cus = 0, per = 0;
+        cap = 1024;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_transpose, 256, 0) == hipSuccess &&
+            cus * per > 0)
+            cap = cus * per;
     }
-    if (block == 512) {
-        hipLaunchKernelGGL(k_batch_solve<512>, dim3((unsigned)grid), dim3(512), 0, s, items, order, count, queue,
+    hipLaunchKernelGGL(k_batch_transpose, dim3((unsigned)(tot.tiles < cap ? tot.tiles : cap)), dim3(256), 0, s,
+                       items, count, tot.tiles);
+    if (block == 512)
+        hipLaunchKernelGGL((k_batch_solve<512, 0>), dim3((unsigned)grid), dim3(512), 0, s, items, order, count, queue,
                            max_switches);
-    } else {
-        hipLaunchKernelGGL(k_batch_solve<256>, dim3((unsigned)grid), dim3(256), 0, s, items, order, count, queue,
+    else
+        hipLaunchKernelGGL((k_batch_solve<256, 0>), dim3((unsigned)grid), dim3(256), 0, s, items, order, count, queue,
                            max_switches);
-    }
+    hipLaunchKernelGGL(k_batch_pairs, dim3((unsigned)tot.pairs), dim3(512), 0, s, items, count);
+    hipLaunchKernelGGL(k_batch_reduce, dim3((unsigned)((tot.agents + 3) / 4)), dim3(256), 0, s, items, count,
+                       tot.agents);
+    if (block == 512)
+        hipLaunchKernelGGL((k_batch_solve<512, 1>), dim3((unsigned)grid), dim3(512), 0, s, items, order, count, queue,
+                           max_switches);
+    else
+        hipLaunchKernelGGL((k_batch_solve<256, 1>), dim3((unsigned)grid), dim3(256), 0, s, items, order, count, queue,
+                           max_switches);
     return hipGetLastError();
 }
 
@@ -464,8 +626,8 @@ int batch_grid_limit(int block) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e = block == 512
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<512>, 512, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<256>, 256, 0);
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<512, 1>, 512, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<256, 1>, 256, 0);
     if (e != hipSuccess || per < 1) return 0;
     return cus * per;
 }

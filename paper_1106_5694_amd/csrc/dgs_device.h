@@ -137,6 +137,20 @@ __device__ __forceinline__ void best2_merge(Best2 &a, u64 k1, u64 k2, int c1) {
     }
 }
 
+// Triangular index p -> (I, K), I <= K < nb, row-major over I.
+__device__ __forceinline__ void pair_of(long long p, int nb, int &I, int &K) {
+    // pairs before row I: I*nb - I*(I-1)/2
+    const double b = 2.0 * nb + 1.0;
+    int i = (int)((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
+    if (i < 0) i = 0;
+    if (i > nb - 1) i = nb - 1;
+    auto start = [&](int r) { return (long long)r * nb - (long long)r * (r - 1) / 2; };
+    while (i > 0 && start(i) > p) --i;
+    while (i + 1 < nb && start(i + 1) <= p) ++i;
+    I = i;
+    K = i + (int)(p - start(i));
+}
+
 // Wave reductions over the lane distances M, M / 2, ..., 1 as template
 // arguments: every exchange is a VALU lane permute whatever the compiler's
 // unrolling does (a distance known only at run time goes through the LDS).

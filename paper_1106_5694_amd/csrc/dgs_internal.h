@@ -158,17 +158,39 @@ struct BatchItem {
     int32_t *AT;       // n x n scratch
     u64 *lists;        // 2n scratch
     int64_t *res;      // [0] f0 [1] f [2] switches [3] re-evaluations [4] status
+    u64 *part;  // batch_part_bytes(n) scratch: the evaluation's per (agent, block) partials
     int n;
-    int tile0;  // first of the instance's ceil(n/64)^2 transpose tiles (running count in table order)
+    int tile0;   // first of the instance's batch_tiles(n) transpose tiles (running count in table order)
+    int pair0;   // first of its batch_pairs(n) evaluation tile pairs (likewise)
+    int agent0;  // first of its n agents (likewise)
 };
-// The batched solve: every instance's transpose over the whole device (tiles = the total
-// count of 64 x 64 tiles), then the persistent solver.
+// Running totals of a batch's item table.
+struct BatchTotals {
+    int64_t tiles = 0, pairs = 0, agents = 0;
+};
+// The batched solve: every instance's transpose over the whole device, the greedy starts
+// (one workgroup per instance), every instance's difference evaluation over the whole
+// device, then the switching (one workgroup per instance).  queue: two words, cleared.
 hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
-                        int64_t max_switches, int64_t tiles, int block, int grid, hipStream_t s);
-// Transpose tiles of an instance of size n.
+                        int64_t max_switches, const BatchTotals &tot, int block, int grid, hipStream_t s);
+// Transpose tiles, evaluation tile pairs and partials bytes of an instance of size n.
 inline int64_t batch_tiles(int n) {
     const int64_t nt = (n + 63) / 64;
     return nt * nt;
+}
+inline int64_t batch_pairs(int n) {
+    const int64_t nt = (n + 63) / 64;
+    return nt * (nt + 1) / 2;
+}
+inline size_t batch_part_bytes(int n) { return (size_t)n * (size_t)((n + 63) / 64) * 2 * sizeof(u64); }
+// Fills a batch item's offsets from the running totals and advances them.
+inline void batch_place(BatchItem &it, BatchTotals &tot) {
+    it.tile0 = (int)tot.tiles;
+    it.pair0 = (int)tot.pairs;
+    it.agent0 = (int)tot.agents;
+    tot.tiles += batch_tiles(it.n);
+    tot.pairs += batch_pairs(it.n);
+    tot.agents += it.n;
 }
 int batch_grid_limit(int block);
 

@@ -97,7 +97,7 @@ struct dgs_batch_plan {
     char *dev = nullptr;
     std::vector<int32_t *> A, tau;  // per instance
     dgs::BatchItem *d_items = nullptr;
-    int64_t tiles = 0;  // transpose tiles of all instances
+    dgs::BatchTotals tot;  // tiles, pairs and agents of all instances
     int32_t *d_order = nullptr;
     int64_t *d_res = nullptr;  // 5 per launch slot
     int32_t *d_queue = nullptr;
@@ -157,10 +157,9 @@ dgs_status run_eager(dgs_batch_plan *p, int block, float *ms) {
         return DGS_E_DEVICE;
     }
     hipStream_t s = p->stream;
-    DGS_HIP(dgs::launch_fill(p->d_queue, 1, 0, s));
+    DGS_HIP(dgs::launch_fill(p->d_queue, 2, 0, s));
     DGS_HIP(hipEventRecord(p->ev0, s));
-    DGS_HIP(dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, p->tiles, block, grid,
-                              s));
+    DGS_HIP(dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, p->tot, block, grid, s));
     DGS_HIP(hipEventRecord(p->ev1, s));
     DGS_HIP(hipMemcpyAsync(p->h_res, p->d_res, (size_t)p->count * 5 * 8, hipMemcpyDeviceToHost, s));
     DGS_HIP(hipStreamSynchronize(s));
@@ -171,9 +170,9 @@ dgs_status run_eager(dgs_batch_plan *p, int block, float *ms) {
 dgs_status capture(dgs_batch_plan *p) {
     hipStream_t s = p->stream;
     DGS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = dgs::launch_fill(p->d_queue, 1, 0, s);
+    hipError_t e = dgs::launch_fill(p->d_queue, 2, 0, s);
     if (e == hipSuccess)
-        e = dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, p->tiles, p->block,
+        e = dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, p->tot, p->block,
                               p->grid, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->h_res, p->d_res, (size_t)p->count * 5 * 8, hipMemcpyDeviceToHost, s);
@@ -261,16 +260,17 @@ dgs_status dgs_batch_plan_create(int32_t count, const int32_t *ns, const dgs_opt
     p->slot_of.resize((size_t)count);
     for (int32_t x = 0; x < count; ++x) p->slot_of[p->inst_of[x]] = x;
 
-    size_t mat = 0, lists = 0, vec = 0;
+    size_t mat = 0, lists = 0, vec = 0, parts = 0;
     for (int32_t n : p->ns) {
         mat += dgs::al256((size_t)n * n * 4);
         lists += dgs::al256((size_t)n * 16);
         vec += dgs::al256((size_t)n * 4);
+        parts += dgs::al256(dgs::batch_part_bytes(n));
     }
     const size_t items_b = dgs::al256((size_t)count * sizeof(dgs::BatchItem));
     const size_t order_b = dgs::al256((size_t)count * 4);
     const size_t res_b = dgs::al256((size_t)count * 5 * 8);
-    const size_t total = 2 * mat + lists + vec + items_b + order_b + res_b + 256;
+    const size_t total = 2 * mat + lists + parts + vec + items_b + order_b + res_b + 256;
     if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess)
         return fail(DGS_E_DEVICE, "hipStreamCreate failed");
     if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
@@ -286,6 +286,8 @@ dgs_status dgs_batch_plan_create(int32_t count, const int32_t *ns, const dgs_opt
     q += mat;
     char *l_base = q;
     q += lists;
+    char *p_base = q;
+    q += parts;
     char *t_base = q;
     q += vec;
     p->d_items = (dgs::BatchItem *)q;
@@ -300,7 +302,7 @@ dgs_status dgs_batch_plan_create(int32_t count, const int32_t *ns, const dgs_opt
     p->tau.assign((size_t)count, nullptr);
     std::vector<dgs::BatchItem> items((size_t)count);
     std::vector<int32_t> order((size_t)count);
-    size_t om = 0, ol = 0, ov = 0;
+    size_t om = 0, ol = 0, ov = 0, op = 0;
     for (int32_t x = 0; x < count; ++x) {
         const int32_t b = p->inst_of[x];
         const int32_t n = p->ns[b];
@@ -313,8 +315,9 @@ dgs_status dgs_batch_plan_create(int32_t count, const int32_t *ns, const dgs_opt
         it.lists = (dgs::u64 *)(l_base + ol);
         it.res = p->d_res + 5 * x;
         it.n = n;
-        it.tile0 = (int)p->tiles;
-        p->tiles += dgs::batch_tiles(n);
+        it.part = (dgs::u64 *)(p_base + op);
+        op += dgs::al256(dgs::batch_part_bytes(n));
+        dgs::batch_place(it, p->tot);
         order[x] = x;
         om += dgs::al256((size_t)n * n * 4);
         ol += dgs::al256((size_t)n * 16);

@@ -39,20 +39,6 @@ constexpr int kScanBlock = 512;  // 8 threads per tile row
 constexpr int kPad = kTile + 1;
 constexpr int kListLen = kScanListLen;
 
-// Triangular index p -> (I, K), I <= K < nb, row-major over I.
-__device__ __forceinline__ void pair_of(long long p, int nb, int &I, int &K) {
-    // pairs before row I: I*nb - I*(I-1)/2
-    const double b = 2.0 * nb + 1.0;
-    int i = (int)((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
-    if (i < 0) i = 0;
-    if (i > nb - 1) i = nb - 1;
-    auto start = [&](int r) { return (long long)r * nb - (long long)r * (r - 1) / 2; };
-    while (i > 0 && start(i) > p) --i;
-    while (i + 1 < nb && start(i + 1) <= p) ++i;
-    I = i;
-    K = i + (int)(p - start(i));
-}
-
 struct ScanParams {
     const int32_t *AT;    // A^T (n x nr); tile row x is row tau[x] of it
     const int32_t *tau;
