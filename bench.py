@@ -392,7 +392,7 @@ def run_batched(args, dgs, torch, gen, np, steps: int, warmup: int, count: int =
         "results_identical": bool(same),
         "autotuned": {"block": block, "grid": grid},
         "roofline": {"bound": "hbm",
-                     "kernel": "k_batch (k_batch_transpose, k_batch_solve<., 0>, k_batch_pairs, k_batch_reduce, "
+                     "kernel": "k_batch (k_batch_solve<., 0> with the transposes, k_batch_pairs, "
                                "k_batch_solve<., 1>: one graph replay)",
                      "achieved": round(gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),

@@ -694,7 +694,7 @@ dgs_status run_batch(const BatchCall &c) {
         }
         DGS_HIP(hipMemcpyAsync(d_items, h_items, m * sizeof(BatchItem), hipMemcpyHostToDevice, s));
         DGS_HIP(hipMemcpyAsync(d_order, h_order, m * 4, hipMemcpyHostToDevice, s));
-        DGS_HIP(launch_fill(d_queue, 2, 0, s));
+        DGS_HIP(launch_fill(d_queue, 3, 0, s));
         const int limit = batch_grid_limit(g_batch_block);
         if (limit < 1) {
             set_error("cannot size the batched solver's grid");

@@ -7,13 +7,13 @@
 //      in order; thread t owns columns t, t + BLOCK, ...; one block max per
 //      agent over the free columns (each thread tracks its own columns'
 //      taken flags in registers);
-//   2. AT = A^T, for every instance at once before the persistent launch
-//      (k_batch_transpose over the whole device: the largest instances' own
-//      workgroups would otherwise spend milliseconds on it);
+//   2. AT = A^T of every instance, tile by tile, by the workgroups of the greedy
+//      launch once no instance is left for them (hidden under the largest
+//      instances' greedy starts, which would otherwise also transpose alone);
 //   3. difference evaluation of every agent (Algorithm 2), for every instance
 //      at once: k_batch_pairs scores the tile pairs of all instances (each
-//      entry read once), k_batch_reduce keeps each agent's best exchange and
-//      the second best as its bound;
+//      entry read once); the switching launch starts each agent from the top-2
+//      of its partials (best exchange, bound);
 //   4. switching (Algorithm 1 as steepest ascent): block max over the
 //      agents' list maxima, apply, update every agent's two changed
 //      candidates, rebuild the two switched agents' lists from the same
@@ -149,12 +149,15 @@ __device__ __forceinline__ void wave_eval_row(const int32_t *A, const int32_t *A
     wave_top2(b1, b2);
 }
 
-// PHASE 0: the greedy start with the range check (tau and res[0], res[4] out); PHASE 1:
-// the switching from the evaluation's lists (k_batch_pairs, k_batch_reduce between the
-// two launches).  Each phase takes the instances from its own queue word, largest first.
+// PHASE 0: the greedy start with the range check (tau and res[0], res[4] out); then,
+// once no instance is left, the transposes AT = A^T of all instances, tiles taken from
+// queue word 2 (they hide under the largest instances' greedy starts).  PHASE 1: the
+// switching, each agent starting from the top-2 of its partials from k_batch_pairs
+// (which runs between the two launches).  Each phase takes the instances from its own
+// queue word, largest first.
 template <int BLOCK, int PHASE>
 __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, const int32_t *order, int count,
-                                                        int32_t *queue, int64_t max_switches) {
+                                                        int32_t *queue, int64_t max_switches, int64_t tiles) {
     constexpr int RPT = kBatchMaxN / BLOCK;  // agents (and columns) per thread
     constexpr int NW = BLOCK / 64;
     __shared__ uint16_t rt[kBatchMaxN];
@@ -255,8 +258,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
         __syncthreads();
         continue;
         } else {
-        // (AT = A^T was written by k_batch_transpose, the evaluation's lists by
-        // k_batch_pairs and k_batch_reduce)
+        // (AT = A^T was written by the greedy launch, the evaluation's partials by
+        // k_batch_pairs)
         if (I.res[4] != DGS_OK) {  // the range check failed (same in every thread)
             __syncthreads();
             continue;
@@ -270,18 +273,22 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
         }
         const int64_t f0 = I.res[0];
         __syncthreads();
+        // ---- 3 (end). each agent's best exchange and bound: the top-2 of its partials --------
         u64 L[RPT][kBM];
         u64 B[RPT];
+        const int nb = (n + 63) >> 6;
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
             const int r = t + u * BLOCK;
 #pragma unroll
             for (int i = 0; i < kBM; ++i) L[u][i] = 0;
-            B[u] = 0;
+            u64 b1 = 0, b2 = 0;
             if (r < n) {
-                L[u][0] = I.lists[2 * r];
-                B[u] = I.lists[2 * r + 1];
+                const u64 *pp = I.part + (size_t)r * nb * 2;
+                for (int x = 0; x < nb; ++x) top2_merge(b1, b2, pp[2 * x], pp[2 * x + 1]);
             }
+            L[u][0] = b1;
+            B[u] = b2;
         }
 
         // ---- 4. switching ---------------------------------------------------------------------
@@ -407,6 +414,52 @@ __global__ __launch_bounds__(BLOCK) void k_batch_solve(const BatchItem *items, c
         __syncthreads();
         }
     }
+    if constexpr (PHASE == 0) {
+        // ---- 2. transposes of all instances: chunks of tiles from queue word 2 --------------
+        // Tile g belongs to the last item x (table order) with items[x].tile0 <= g; a chunk
+        // searches once and then walks forward.
+        constexpr int kChunk = 8;
+        int32_t(*tile)[65] = reinterpret_cast<int32_t(*)[65]>(&rowbuf[0][0]);  // 64 x 65 of the row buffers
+        static_assert(NW * (kBatchMaxN + 64) >= 64 * 65, "tile fits the row buffers");
+        for (;;) {
+            if (t == 0) s_item = atomicAdd(&queue[2], kChunk);
+            __syncthreads();
+            const int64_t g0 = s_item;
+            __syncthreads();
+            if (g0 >= tiles) break;
+            int x = 0, hi = count - 1;
+            while (x < hi) {
+                const int mid = (x + hi + 1) >> 1;
+                if (items[mid].tile0 <= g0)
+                    x = mid;
+                else
+                    hi = mid - 1;
+            }
+            for (int64_t g = g0; g < g0 + kChunk && g < tiles; ++g) {
+                while (x + 1 < count && items[x + 1].tile0 <= g) ++x;
+                const int32_t *A = items[x].A;
+                int32_t *AT = items[x].AT;
+                const int n = items[x].n, nt = (n + 63) >> 6;
+                const int local = (int)(g - items[x].tile0), bi = local / nt, bj = local % nt;
+                constexpr int RW = 64 / NW;  // rows per wave
+                int v[RW];
+#pragma unroll
+                for (int k = 0; k < RW; ++k) {
+                    const int row = bi * 64 + w + NW * k, col = bj * 64 + lane;
+                    v[k] = (row < n && col < n) ? A[(int64_t)row * n + col] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < RW; ++k) tile[w + NW * k][lane] = v[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < RW; ++k) {
+                    const int col = bj * 64 + w + NW * k, row = bi * 64 + lane;
+                    if (col < n && row < n) AT[(int64_t)col * n + row] = tile[lane][w + NW * k];
+                }
+                __syncthreads();  // the tile is rewritten next
+            }
+        }
+    }
 }
 
 // The difference evaluation of every instance over the whole device: workgroup g scores
@@ -524,102 +577,7 @@ __global__ __launch_bounds__(512) void k_batch_pairs(const BatchItem *items, int
     }
 }
 
-// One wave per agent of the batch (the last item x with items[x].agent0 <= agent): the
-// top-2 of its block partials into the instance's lists (best, then the bound).
-__global__ __launch_bounds__(256) void k_batch_reduce(const BatchItem *items, int count, int64_t agents) {
-    const int64_t a = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (a >= agents) return;
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].agent0 <= a)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    if (items[lo].res[4] != DGS_OK) return;
-    const int n = items[lo].n, nb = (n + 63) >> 6, r = (int)(a - items[lo].agent0);
-    const u64 *p = items[lo].part + (size_t)r * nb * 2;
-    u64 b1 = 0, b2 = 0;
-    for (int x = lane; x < nb; x += 64) top2_merge(b1, b2, p[2 * x], p[2 * x + 1]);
-    wave_top2(b1, b2);
-    if (lane == 0) {
-        items[lo].lists[2 * r] = b1;
-        items[lo].lists[2 * r + 1] = b2;
-    }
-}
-
-// AT = A^T of every instance in 64 x 64 tiles over the whole device.  Global tile g
-// belongs to the last item x (in table order) with items[x].tile0 <= g.
-__global__ __launch_bounds__(256) void k_batch_transpose(const BatchItem *items, int count, int64_t tiles) {
-    __shared__ int32_t tile[64][65];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (int64_t g = blockIdx.x; g < tiles; g += gridDim.x) {
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].tile0 <= g)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const int32_t *A = items[lo].A;
-        int32_t *AT = items[lo].AT;
-        const int n = items[lo].n, nt = (n + 63) >> 6;
-        const int local = (int)(g - items[lo].tile0), bi = local / nt, bj = local % nt;
-        int v[16];  // wave w: rows w, w + 4, ..., all 16 loads in flight
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int row = bi * 64 + w + 4 * k, col = bj * 64 + lane;
-            v[k] = (row < n && col < n) ? A[(int64_t)row * n + col] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) tile[w + 4 * k][lane] = v[k];
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int col = bj * 64 + w + 4 * k, row = bi * 64 + lane;
-            if (col < n && row < n) AT[(int64_t)col * n + row] = tile[lane][w + 4 * k];
-        }
-        __syncthreads();  // the tile is rewritten next
-    }
-}
-
 }  // namespace
-
-hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
-                        int64_t max_switches, const BatchTotals &tot, int block, int grid, hipStream_t s) {
-    if (count < 1) return hipSuccess;
-    static int cap = -1;
-    if (cap < 0) {
-        int dev = 0, cus = 0, per = 0;
-        cap = 1024;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_transpose, 256, 0) == hipSuccess &&
-            cus * per > 0)
-            cap = cus * per;
-    }
-    hipLaunchKernelGGL(k_batch_transpose, dim3((unsigned)(tot.tiles < cap ? tot.tiles : cap)), dim3(256), 0, s,
-                       items, count, tot.tiles);
-    if (block == 512)
-        hipLaunchKernelGGL((k_batch_solve<512, 0>), dim3((unsigned)grid), dim3(512), 0, s, items, order, count, queue,
-                           max_switches);
-    else
-        hipLaunchKernelGGL((k_batch_solve<256, 0>), dim3((unsigned)grid), dim3(256), 0, s, items, order, count, queue,
-                           max_switches);
-    hipLaunchKernelGGL(k_batch_pairs, dim3((unsigned)tot.pairs), dim3(512), 0, s, items, count);
-    hipLaunchKernelGGL(k_batch_reduce, dim3((unsigned)((tot.agents + 3) / 4)), dim3(256), 0, s, items, count,
-                       tot.agents);
-    if (block == 512)
-        hipLaunchKernelGGL((k_batch_solve<512, 1>), dim3((unsigned)grid), dim3(512), 0, s, items, order, count, queue,
-                           max_switches);
-    else
-        hipLaunchKernelGGL((k_batch_solve<256, 1>), dim3((unsigned)grid), dim3(256), 0, s, items, order, count, queue,
-                           max_switches);
-    return hipGetLastError();
-}
 
 int batch_grid_limit(int block) {
     int dev = 0, cus = 0, per = 0;
@@ -630,6 +588,30 @@ int batch_grid_limit(int block) {
                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<256, 1>, 256, 0);
     if (e != hipSuccess || per < 1) return 0;
     return cus * per;
+}
+
+hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
+                        int64_t max_switches, const BatchTotals &tot, int block, int grid, hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    // the greedy launch fills the device: workgroups without an instance transpose at once
+    static int full[2] = {-1, -1};
+    int &f = full[block == 512];
+    if (f < 0) f = batch_grid_limit(block);
+    const int grid0 = f > grid ? f : grid;
+    if (block == 512)
+        hipLaunchKernelGGL((k_batch_solve<512, 0>), dim3((unsigned)grid0), dim3(512), 0, s, items, order, count,
+                           queue, max_switches, tot.tiles);
+    else
+        hipLaunchKernelGGL((k_batch_solve<256, 0>), dim3((unsigned)grid0), dim3(256), 0, s, items, order, count,
+                           queue, max_switches, tot.tiles);
+    hipLaunchKernelGGL(k_batch_pairs, dim3((unsigned)tot.pairs), dim3(512), 0, s, items, count);
+    if (block == 512)
+        hipLaunchKernelGGL((k_batch_solve<512, 1>), dim3((unsigned)grid), dim3(512), 0, s, items, order, count, queue,
+                           max_switches, tot.tiles);
+    else
+        hipLaunchKernelGGL((k_batch_solve<256, 1>), dim3((unsigned)grid), dim3(256), 0, s, items, order, count, queue,
+                           max_switches, tot.tiles);
+    return hipGetLastError();
 }
 
 }  // namespace dgs

@@ -162,15 +162,16 @@ struct BatchItem {
     int n;
     int tile0;   // first of the instance's batch_tiles(n) transpose tiles (running count in table order)
     int pair0;   // first of its batch_pairs(n) evaluation tile pairs (likewise)
-    int agent0;  // first of its n agents (likewise)
+    int pad;
 };
 // Running totals of a batch's item table.
 struct BatchTotals {
-    int64_t tiles = 0, pairs = 0, agents = 0;
+    int64_t tiles = 0, pairs = 0;
 };
-// The batched solve: every instance's transpose over the whole device, the greedy starts
-// (one workgroup per instance), every instance's difference evaluation over the whole
-// device, then the switching (one workgroup per instance).  queue: two words, cleared.
+// The batched solve: the greedy starts (one workgroup per instance; then the same
+// workgroups transpose every instance), every instance's difference evaluation over the
+// whole device, then the switching (one workgroup per instance).  queue: three words,
+// cleared.
 hipError_t launch_batch(const BatchItem *items, const int32_t *order, int count, int32_t *queue,
                         int64_t max_switches, const BatchTotals &tot, int block, int grid, hipStream_t s);
 // Transpose tiles, evaluation tile pairs and partials bytes of an instance of size n.
@@ -187,10 +188,9 @@ inline size_t batch_part_bytes(int n) { return (size_t)n * (size_t)((n + 63) / 6
 inline void batch_place(BatchItem &it, BatchTotals &tot) {
     it.tile0 = (int)tot.tiles;
     it.pair0 = (int)tot.pairs;
-    it.agent0 = (int)tot.agents;
+    it.pad = 0;
     tot.tiles += batch_tiles(it.n);
     tot.pairs += batch_pairs(it.n);
-    tot.agents += it.n;
 }
 int batch_grid_limit(int block);
 

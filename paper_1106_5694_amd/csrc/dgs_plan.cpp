@@ -157,7 +157,7 @@ dgs_status run_eager(dgs_batch_plan *p, int block, float *ms) {
         return DGS_E_DEVICE;
     }
     hipStream_t s = p->stream;
-    DGS_HIP(dgs::launch_fill(p->d_queue, 2, 0, s));
+    DGS_HIP(dgs::launch_fill(p->d_queue, 3, 0, s));
     DGS_HIP(hipEventRecord(p->ev0, s));
     DGS_HIP(dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, p->tot, block, grid, s));
     DGS_HIP(hipEventRecord(p->ev1, s));
@@ -170,7 +170,7 @@ dgs_status run_eager(dgs_batch_plan *p, int block, float *ms) {
 dgs_status capture(dgs_batch_plan *p) {
     hipStream_t s = p->stream;
     DGS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = dgs::launch_fill(p->d_queue, 2, 0, s);
+    hipError_t e = dgs::launch_fill(p->d_queue, 3, 0, s);
     if (e == hipSuccess)
         e = dgs::launch_batch(p->d_items, p->d_order, p->count, p->d_queue, p->max_switches, p->tot, p->block,
                               p->grid, s);
