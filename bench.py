@@ -42,7 +42,7 @@ SINGLE = {
 WORKLOADS = sorted(SINGLE) + ["batched512", "serving"]
 
 KERNELS = {"range": "k_range_check", "init": "k_greedy_pipe",
-           "layout": "k_transpose+k_benefits", "scan": "k_scan_pairs+k_scan_reduce",
+           "layout": "k_transpose+k_permuted+k_benefits", "scan": "k_scan_pairs+k_scan_reduce",
            "switch": "k_switch_v3"}
 KERNEL_SOURCES = {"k_switch_v3": "dgs_switch3.hip", "k_scan_pairs+k_scan_reduce": "dgs_scan.hip",
                   "k_batch": "dgs_batch.hip"}
@@ -56,7 +56,7 @@ def algorithmic_bytes(phase: str, n: int, switches: int, rescans: int) -> int:
     if phase == "init":
         return 4 * nn  # greedy reads every entry once
     if phase == "layout":
-        return 8 * nn  # transpose (read + write)
+        return 16 * nn  # transpose and the permuted copy W (each read + write)
     if phase == "scan":
         return 4 * nn  # every exchange pair (i, k) needs a_i,tau(k) and a_k,tau(i) once
     if phase == "switch":

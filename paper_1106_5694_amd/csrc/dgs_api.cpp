@@ -93,6 +93,7 @@ struct Workspace {
     bool has_acopy = false;
     int32_t *acopy = nullptr;  // device copy of a host benefit matrix
     int32_t *at = nullptr;
+    int32_t *wperm = nullptr;  // W[r][c] = a[r][tau(c)] of a square steepest-ascent solve (or null)
     char *vec = nullptr;  // vectors + scratch
     size_t vec_bytes = 0;
     hipMemPool_t pool = nullptr;  // buffers from this pool (freed on `stream`), else from hipMalloc
@@ -187,7 +188,7 @@ VecLayout vec_layout(int32_t n) {
 
 void free_ws(Workspace *w) {
     if (!w) return;
-    for (void *p : {(void *)w->acopy, (void *)w->at, (void *)w->vec}) {
+    for (void *p : {(void *)w->acopy, (void *)w->at, (void *)w->wperm, (void *)w->vec}) {
         if (!p) continue;
         if (w->pool)
             (void)hipFreeAsync(p, w->stream);
@@ -199,8 +200,9 @@ void free_ws(Workspace *w) {
 
 // Device buffers for an instance of n agents (nr of them real: matrices of
 // nr x n entries): from the cache (pool == NULL) or from `pool`, ordered on
-// `stream`.
-dgs_status alloc_ws(int32_t n, int32_t nr, bool need_acopy, hipMemPool_t pool, hipStream_t stream, Workspace **out) {
+// `stream`.  need_w: also the n x n matrix W of the steepest-ascent loop.
+dgs_status alloc_ws(int32_t n, int32_t nr, bool need_acopy, bool need_w, hipMemPool_t pool, hipStream_t stream,
+                    Workspace **out) {
     const size_t mat = (size_t)nr * (size_t)n * sizeof(int32_t);
     if (!pool) {
         std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -208,6 +210,7 @@ dgs_status alloc_ws(int32_t n, int32_t nr, bool need_acopy, hipMemPool_t pool, h
             // do not hand a huge workspace to a tiny problem
             if (it->first > 2 * n + 1024) break;
             if (need_acopy && !it->second->has_acopy) continue;
+            if (need_w && !it->second->wperm) continue;
             if (it->second->mat_bytes < mat) continue;
             *out = it->second;
             g_ws_free.erase(it);
@@ -232,6 +235,7 @@ dgs_status alloc_ws(int32_t n, int32_t nr, bool need_acopy, hipMemPool_t pool, h
         w->has_acopy = true;
     }
     if (!dev((void **)&w->at, mat)) return fail("transpose");
+    if (need_w && !dev((void **)&w->wperm, mat)) return fail("permuted benefits");
     w->vec_bytes = vec_layout(n).total;
     if (!dev((void **)&w->vec, w->vec_bytes)) return fail("vectors");
     *out = w;
@@ -412,7 +416,9 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     dgs_status st = h ? DGS_OK : acquire_host(&h);
     if (st != DGS_OK) return st;
     Workspace *w = c.ws;
-    st = w ? DGS_OK : alloc_ws(n, nr, !c.dev, c.pool, s, &w);
+    // the steepest-ascent loop of a square instance reads W (a caller-held workspace has none)
+    const bool steepest = mode == Mode::Solve && !c.parallel && !c.lazy && n >= 2;
+    st = w ? DGS_OK : alloc_ws(n, nr, !c.dev, steepest && nr == n, c.pool, s, &w);
     if (st != DGS_OK) {
         if (!c.host) release_host(h);
         return st;
@@ -433,6 +439,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     }
     const int32_t *A = c.dev ? c.benefit : w->acopy;
     Instance I = carve(w, A, n, nr);
+    I.W = steepest && nr == n ? w->wperm : nullptr;
     if (!c.dev) DGS_HIP(hipMemcpyAsync(w->acopy, c.benefit, mat, hipMemcpyHostToDevice, s));
 
     DGS_HIP(hipEventRecord(h->ev0, s));
@@ -470,6 +477,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     }
     DGS_HIP(mark(DGS_PHASE_LAYOUT));
     if (!gg) DGS_HIP(launch_transpose(A, I.AT, nr, n, s));
+    if (I.W) DGS_HIP(launch_permuted(A, I.tau, n, I.W, s));
     DGS_HIP(launch_benefits(A, I.tau, n, nr, I.d, I.stats + 2, s));
     DGS_HIP(mark(DGS_PHASE_SCAN));
     if (c.parallel && mode == Mode::Solve)

@@ -12,10 +12,14 @@
 // gain of the 2-exchange between agents r and c is
 //   g(r, c) = W[r][c] + W[c][r] - d[r] - d[c],  g(r, c) = g(c, r),
 // and column c of W is row tau(c) of AT, so the evaluation reads AT through
-// tau and W is never built.  Agent r's candidate towards agent c is ranked
+// tau.  The steepest-ascent switching loop of a square instance reads rows of
+// W, so W is built for it once (k_permuted) and the loop keeps it current: a
+// switch changes two of its columns.  Agent r's candidate towards agent c is ranked
 // by the packed key (gain, job tau(c)): larger gain first, lower job on ties
 // (ADE, Algorithm 2, takes the first strictly better job in index order).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "dgs_device.h"
@@ -79,6 +83,56 @@ __global__ __launch_bounds__(256) void k_transpose(const int32_t *__restrict__ A
     }
 }
 
+// W[r][c] = a[r][tau(c)] for a square instance: one workgroup per row r, the
+// row staged through LDS in chunks of kPermChunk columns (one chunk for
+// n <= kPermChunk), then every column c takes its entry tau(c) from LDS.  With
+// VEC4 (n a multiple of 4) rows, tau and W move 16 bytes per thread and access.
+constexpr int kPermChunk = 16384;
+constexpr int kPermThreads = 512;
+template <bool VEC4>
+__global__ __launch_bounds__(kPermThreads) void k_permuted(const int32_t *__restrict__ A,
+                                                             const int32_t *__restrict__ tau, int n,
+                                                             int32_t *__restrict__ W) {
+    extern __shared__ int4 prow4[];  // min(n, kPermChunk) entries
+    int32_t *prow = reinterpret_cast<int32_t *>(prow4);
+    const int t = threadIdx.x;
+    const int32_t *Ar = A + (int64_t)blockIdx.x * n;
+    int32_t *Wr = W + (int64_t)blockIdx.x * n;
+    for (int h0 = 0; h0 < n; h0 += kPermChunk) {
+        const int len = min(kPermChunk, n - h0);
+        if (VEC4) {
+            const int4 *src = reinterpret_cast<const int4 *>(Ar + h0);
+            for (int i = t; i < len / 4; i += kPermThreads) prow4[i] = src[i];
+        } else {
+            for (int i = t; i < len; i += kPermThreads) prow[i] = Ar[h0 + i];
+        }
+        __syncthreads();
+        if (VEC4) {
+            const int4 *tv = reinterpret_cast<const int4 *>(tau);
+            int4 *dst = reinterpret_cast<int4 *>(Wr);
+            for (int c = t; c < n / 4; c += kPermThreads) {
+                const int4 j = tv[c];
+                const int j0 = j.x - h0, j1 = j.y - h0, j2 = j.z - h0, j3 = j.w - h0;
+                if (len == n) {  // one chunk: every entry of a permutation is in LDS
+                    auto at = [&](int j) { return (unsigned)j < (unsigned)len ? prow[j] : 0; };
+                    dst[c] = make_int4(at(j0), at(j1), at(j2), at(j3));
+                } else {
+                    if ((unsigned)j0 < (unsigned)len) Wr[4 * c] = prow[j0];
+                    if ((unsigned)j1 < (unsigned)len) Wr[4 * c + 1] = prow[j1];
+                    if ((unsigned)j2 < (unsigned)len) Wr[4 * c + 2] = prow[j2];
+                    if ((unsigned)j3 < (unsigned)len) Wr[4 * c + 3] = prow[j3];
+                }
+            }
+        } else {
+            for (int c = t; c < n; c += kPermThreads) {
+                const int j = tau[c] - h0;
+                if ((unsigned)j < (unsigned)len) Wr[c] = prow[j];
+            }
+        }
+        __syncthreads();  // the next chunk overwrites the row buffer
+    }
+}
+
 // d[r] = a[r][tau(r)] (0 for the virtual agents r >= nr) and f0 = sum of d.
 __global__ __launch_bounds__(256) void k_benefits(const int32_t *__restrict__ A, const int32_t *__restrict__ tau,
                                                     int n, int nr, int32_t *d, unsigned long long *f0) {
@@ -133,6 +187,21 @@ hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, 
 hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t rows, int32_t cols, hipStream_t s) {
     const unsigned tc = (unsigned)((cols + 63) / 64), tr = (unsigned)((rows + 63) / 64);
     hipLaunchKernelGGL(k_transpose, dim3(tc, tr), dim3(256), 0, s, A, AT, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_permuted(const int32_t *A, const int32_t *tau, int32_t n, int32_t *W, hipStream_t s) {
+    if (n < 1) return hipSuccess;
+    const int shm = (int)(std::min(n, kPermChunk) * sizeof(int32_t));
+    auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+    const bool vec4 = n % 4 == 0 && al16(A) && al16(tau) && al16(W);  // every row then starts 16-byte aligned
+    const void *kern = vec4 ? (const void *)k_permuted<true> : (const void *)k_permuted<false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+    if (e != hipSuccess) return e;
+    if (vec4)
+        hipLaunchKernelGGL(k_permuted<true>, dim3((unsigned)n), dim3(kPermThreads), (unsigned)shm, s, A, tau, n, W);
+    else
+        hipLaunchKernelGGL(k_permuted<false>, dim3((unsigned)n), dim3(kPermThreads), (unsigned)shm, s, A, tau, n, W);
     return hipGetLastError();
 }
 

@@ -39,6 +39,14 @@
 // Otherwise the switch (i*, j*) with partner k = sigma(j*) is applied and
 // every other agent r receives its two changed candidates exactly:
 // g(r, i*) for job j* and g(r, k) for job tau(i*).
+//
+// Loads: g(r, x) = a[r][tau(x)] + a[x][tau(r)] - d(r) - d(x).  The first term
+// is row tau(x) of AT at column r, read coalesced.  The second is, for an
+// agent r that has not switched in this loop, row x of the matrix
+// W[x][c] = a[x][tau0(c)] (tau0: the start assignment; built once for square
+// instances) at column r: coalesced too, where a[x][tau(r)] from A costs one
+// cache line per agent.  Agents that have switched read A.  W is never written
+// here.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -212,6 +220,7 @@ struct V3Params {
     const int32_t *d;      // start benefits d[c] = a[c][tau(c)]
     const u64 *lists;      // full-evaluation candidate lists [n][kScanListLen] (gain, job) keys
     const u64 *bb;         // full-evaluation bounds
+    const int32_t *W;      // USEW: n x n, W[x][c] = a[x][tau0(c)] for the start assignment tau0
     u64 *words;            // 2 * G * kW exchange words
     int64_t *stats;        // [0] switches [1] gain sum [3] re-evaluations [4] stalled rounds
     const int32_t *flags;  // [0] != 0: range check failed, do nothing
@@ -227,8 +236,10 @@ __device__ __forceinline__ void put_word(u64 *p, u64 w) {
 
 // NPER: gathered words per thread (G * kW <= NPER * kT).  VIRT: the instance
 // has virtual agents (nr < n; the square path compiles without their tests).
-template <int NPER, bool VIRT>
+// USEW: square instances only; rows of A through the start assignment are read from W.
+template <int NPER, bool VIRT, bool USEW>
 __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
+    static_assert(!(VIRT && USEW), "W is kept for square instances only");
     extern __shared__ __align__(16) u64 wl[];  // gathered words, G x (words of the round)
     // values reduced by this workgroup in a round: 0 best keys, 1 pending keys, 2 + j the
     // shares for the round's j-th target (written at the end of the previous round)
@@ -257,6 +268,7 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
     const int lane = t & 63, wave = t >> 6;
 
     int tr = 0, dr = 0;
+    bool moved = false;  // USEW: this agent has switched (its column of W is stale)
     u64 L[kM];
 #pragma unroll
     for (int i = 0; i < kM; ++i) L[i] = 0;
@@ -543,8 +555,14 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         int tr2 = tr;  // job after this round's switch
         if (mine && !stall) tr2 = r == is ? js : (r == k ? j0 : tr);
         int a1 = 0, a2 = 0, w1 = 0, w2 = 0;
+        const bool wcur = USEW && !moved;  // a[x][tau(r)] = W[x][r]
         if (mine && !stall && r != is && r != k) {
-            if (!VIRT) {
+            if (USEW) {
+                a1 = P.AT[(int64_t)js * nt_ + r];  // a[r][j*]
+                a2 = P.AT[(int64_t)j0 * nt_ + r];  // a[r][j0]
+                w1 = *(wcur ? P.W + (int64_t)is * nn + r : P.A + (int64_t)is * nn + tr);  // a[i*][tau(r)]
+                w2 = *(wcur ? P.W + (int64_t)k * nn + r : P.A + (int64_t)k * nn + tr);    // a[k][tau(r)]
+            } else if (!VIRT) {
                 a1 = P.AT[(int64_t)js * nt_ + r];  // a[r][j*]
                 a2 = P.AT[(int64_t)j0 * nt_ + r];  // a[r][j0]
                 w1 = P.A[(int64_t)is * nn + tr];   // a[i*][tau(r)]
@@ -568,7 +586,10 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             ra[dd] = rb[dd] = 0;
             if (ok) {
                 if (real) ra[dd] = P.AT[(int64_t)nx_tau[dd] * nt_ + r];  // a[r][tau(x)] (real == mine unless VIRT)
-                rb[dd] = P.A[(int64_t)x * nn + tr2];                     // a[x][tau(r)] after the switch
+                if (USEW)  // a[x][tau(r)] after the switch (W's column r is stale if r switches now)
+                    rb[dd] = *(wcur && r != is && r != k ? P.W + (int64_t)x * nn + r : P.A + (int64_t)x * nn + tr2);
+                else
+                    rb[dd] = P.A[(int64_t)x * nn + tr2];  // a[x][tau(r)] after the switch
             }
         }
         int dis = 0, dk = 0;
@@ -657,6 +678,7 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                 inflight = switched ? false : inflight;
                 s0 = r == is ? 0 : (r == k ? le_key(-gw, j0, t) : le_key(g1, tr, t));  // g(k, i*) after the switch
                 s1 = r == k ? 0 : (r == is ? le_key(-gw, js, t) : le_key(g2, tr, t));  // g(i*, k) after the switch
+                moved = moved || switched;
                 tr = tr2;
                 dr = r == is ? dis : (r == k ? dk : dr);
             }
@@ -712,6 +734,7 @@ hipError_t launch_switch_v3(const Instance &I, int64_t max_switches, void *words
     P.d = I.d;
     P.lists = I.lists;
     P.bb = I.bb;
+    P.W = I.W;
     P.words = (u64 *)words;
     P.stats = I.stats;
     P.flags = I.flags;
@@ -723,10 +746,13 @@ hipError_t launch_switch_v3(const Instance &I, int64_t max_switches, void *words
     if (grid < 1 || grid > kMaxG) return hipErrorInvalidValue;
     const size_t shm = (size_t)grid * kW * sizeof(u64);
     // the narrow gather when every workgroup's words fit 8 per thread
-    const bool narrow = grid * kW <= 8 * kT, virt = I.nr < I.n;
-    const void *kern = narrow ? (virt ? (const void *)k_switch_v3<8, true> : (const void *)k_switch_v3<8, false>)
-                              : (virt ? (const void *)k_switch_v3<kGatherPer, true>
-                                      : (const void *)k_switch_v3<kGatherPer, false>);
+    const bool narrow = grid * kW <= 8 * kT, virt = I.nr < I.n, usew = I.W != nullptr && !virt;
+    const void *kern = narrow ? (virt   ? (const void *)k_switch_v3<8, true, false>
+                                 : usew ? (const void *)k_switch_v3<8, false, true>
+                                        : (const void *)k_switch_v3<8, false, false>)
+                              : (virt   ? (const void *)k_switch_v3<kGatherPer, true, false>
+                                 : usew ? (const void *)k_switch_v3<kGatherPer, false, true>
+                                        : (const void *)k_switch_v3<kGatherPer, false, false>);
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     void *args[] = {&P};

@@ -36,7 +36,7 @@ def test_algorithmic_bytes_per_unit(n):
     nn = n * n
     assert bench.algorithmic_bytes("range", n, 0, 0) == 4 * nn
     assert bench.algorithmic_bytes("scan", n, 0, 0) == 4 * nn
-    assert bench.algorithmic_bytes("layout", n, 0, 0) == 8 * nn  # transpose: read + write
+    assert bench.algorithmic_bytes("layout", n, 0, 0) == 16 * nn  # transpose and W: each read + write
     # per switch 16n B; the loop's own re-evaluations (8n B each) are reported apart
     assert bench.algorithmic_bytes("switch", n, 3, 5) == 16 * n * 3
     assert bench.reevaluation_bytes(n, 5) == 8 * n * 5

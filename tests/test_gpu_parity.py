@@ -206,6 +206,14 @@ def test_lowrank20480_wide_gather(dgs):
     assert h2 == full["tau_sha256"]
 
 
+def test_ragged_large_prefix(dgs):
+    """n = 16387: rows that are not a multiple of four and longer than one
+    LDS chunk when the switching loop's permuted copy of A is built; the first
+    300 switches from the greedy start match the oracle's."""
+    A = gen.lowrank_matrix(16387, 5)
+    check_against_oracle(dgs, A, max_switches=300, what="ragged large prefix")
+
+
 def test_plain_dgs_solve(dgs):
     """The three-argument dgs_solve, called through ctypes with host buffers."""
     import ctypes
