@@ -319,6 +319,7 @@ struct Call {
     bool coop = true;  // cooperative switching launch (else the caller owns co-residency)
     bool parallel = false;  // Parallel DGS rounds instead of the switching loop (max_switches = max rounds)
     bool lazy = false;      // lazy DGS passes (Algorithm 1 with stale stored bests) instead of the switching loop
+    bool permuted = true;   // a square steepest-ascent solve builds W for its switching loop (+4n^2 bytes)
     hipMemPool_t pool = nullptr;  // device buffers from this pool (stream-ordered) instead of the cache
     Workspace *ws = nullptr;      // a workspace the caller holds (not taken from or returned to the cache)
     HostRes *host = nullptr;      // host resources the caller holds (likewise)
@@ -418,7 +419,8 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     Workspace *w = c.ws;
     // the steepest-ascent loop of a square instance reads W (a caller-held workspace has none)
     const bool steepest = mode == Mode::Solve && !c.parallel && !c.lazy && n >= 2;
-    st = w ? DGS_OK : alloc_ws(n, nr, !c.dev, steepest && nr == n, c.pool, s, &w);
+    const bool use_w = steepest && nr == n && c.permuted;
+    st = w ? DGS_OK : alloc_ws(n, nr, !c.dev, use_w, c.pool, s, &w);
     if (st != DGS_OK) {
         if (!c.host) release_host(h);
         return st;
@@ -439,7 +441,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     }
     const int32_t *A = c.dev ? c.benefit : w->acopy;
     Instance I = carve(w, A, n, nr);
-    I.W = steepest && nr == n ? w->wperm : nullptr;
+    I.W = use_w ? w->wperm : nullptr;
     if (!c.dev) DGS_HIP(hipMemcpyAsync(w->acopy, c.benefit, mat, hipMemcpyHostToDevice, s));
 
     DGS_HIP(hipEventRecord(h->ev0, s));
@@ -811,6 +813,7 @@ dgs_status solve_internal(const int32_t *benefit, int32_t n, int32_t *assign_out
     c.profile = false;
     c.coop = coop;
     c.pool = pool;
+    c.permuted = false;  // the server's requests keep their footprint at two matrices
     c.stream = s ? s : g_ctx.stream;
     return run_instance(c, Mode::Solve, assign_out, nullptr, nullptr, res);
 }

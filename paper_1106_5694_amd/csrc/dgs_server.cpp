@@ -238,9 +238,9 @@ extern "C" {
 uint64_t dgs_server_footprint(int32_t n) {
     const uint64_t nn = (uint64_t)n * (uint64_t)n;
     if (n <= dgs::kBatchMaxN) return 2 * 4 * nn + 32 * (uint64_t)n + 4096;  // copy + transpose
-    // device copy, transpose and the switching loop's permuted copy W, evaluation partials, vectors
-    // and lists
-    return 3 * 4 * nn + 2 * 16 * (uint64_t)n * (((uint64_t)n + 63) / 64) + 256 * (uint64_t)n + (1u << 20);
+    // device copy + transpose (no permuted copy W: the switching loop reads A), evaluation partials,
+    // vectors and lists
+    return 2 * 4 * nn + 2 * 16 * (uint64_t)n * (((uint64_t)n + 63) / 64) + 256 * (uint64_t)n + (1u << 20);
 }
 
 dgs_status dgs_server_create(const dgs_server_config *cfg, dgs_server **out) {
