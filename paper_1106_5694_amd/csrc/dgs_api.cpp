@@ -200,7 +200,8 @@ void free_ws(Workspace *w) {
 
 // Device buffers for an instance of n agents (nr of them real: matrices of
 // nr x n entries): from the cache (pool == NULL) or from `pool`, ordered on
-// `stream`.  need_w: also the n x n matrix W of the steepest-ascent loop.
+// `stream`.  need_w: also the n x n matrix W of the steepest-ascent loop (left out, not an
+// error, when it does not fit).
 dgs_status alloc_ws(int32_t n, int32_t nr, bool need_acopy, bool need_w, hipMemPool_t pool, hipStream_t stream,
                     Workspace **out) {
     const size_t mat = (size_t)nr * (size_t)n * sizeof(int32_t);
@@ -235,7 +236,11 @@ dgs_status alloc_ws(int32_t n, int32_t nr, bool need_acopy, bool need_w, hipMemP
         w->has_acopy = true;
     }
     if (!dev((void **)&w->at, mat)) return fail("transpose");
-    if (need_w && !dev((void **)&w->wperm, mat)) return fail("permuted benefits");
+    if (need_w && !dev((void **)&w->wperm, mat)) {
+        // W only speeds the switching loop up: without it the loop reads A (same results)
+        w->wperm = nullptr;
+        (void)hipGetLastError();  // the failed allocation must not surface at a later launch check
+    }
     w->vec_bytes = vec_layout(n).total;
     if (!dev((void **)&w->vec, w->vec_bytes)) return fail("vectors");
     *out = w;
