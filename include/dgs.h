@@ -33,7 +33,12 @@
  *
  * Memory: the caller owns every buffer it passes.  Inputs are only read for
  * the duration of the call (server: until the request completes).  The
- * library owns its device memory and streams.
+ * library owns its device memory and streams.  A solve holds the transpose
+ * of the benefit matrix (4 n*m bytes) and, for a host matrix, a device copy
+ * of it; the default steepest-ascent solve of a square instance also holds
+ * a copy permuted by the start assignment (4 n^2 bytes), which is left out
+ * (same results, slower switching) when it does not fit and for server
+ * requests.
  */
 #ifndef DGS_H
 #define DGS_H
