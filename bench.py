@@ -6,7 +6,7 @@ evaluation of every agent, switching until no improving 2-exchange is
 left) of the n = 16384 low-rank-plus-noise instance, with the benefit
 matrix already resident in HBM.  Prints one JSON line; the line also
 carries a short measurement of the batched workload (512 instances in one
-graph-captured launch, against a loop of single-instance solves).
+graph replay of three launches, against a loop of single-instance solves).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
@@ -343,9 +343,10 @@ def run_rect(args, dgs, torch, gen, np, steps: int = 2) -> dict:
 
 def run_batched(args, dgs, torch, gen, np, steps: int, warmup: int, count: int = 512) -> dict:
     """The batched workload: `count` instances, n log-uniform in [64, 2048],
-    iid uniform benefits in [0, 10000), solved by one graph-captured
-    persistent launch per step; against a loop of single-instance solves of
-    the same device-resident instances."""
+    iid uniform benefits in [0, 10000), solved by one replay per step of a
+    captured graph of three launches (greedy starts with the transposes,
+    evaluation, switching); against a loop of single-instance solves of the
+    same device-resident instances."""
     t0 = time.perf_counter()
     ns = [int(n) for n in gen.loguniform_sizes(count, 64, 2048, args.seed)]
     As = gen.batch_instances(count, 64, 2048, args.seed)
