@@ -93,7 +93,7 @@ struct Workspace {
     bool has_acopy = false;
     int32_t *acopy = nullptr;  // device copy of a host benefit matrix
     int32_t *at = nullptr;
-    int32_t *wperm = nullptr;  // W[r][c] = a[r][tau(c)] of a square steepest-ascent solve (or null)
+    int32_t *wperm = nullptr;  // W[r][c] = a[r][tau0(c)] of a square steepest-ascent solve (or null)
     char *vec = nullptr;  // vectors + scratch
     size_t vec_bytes = 0;
     hipMemPool_t pool = nullptr;  // buffers from this pool (freed on `stream`), else from hipMalloc
@@ -424,7 +424,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     Workspace *w = c.ws;
     // the steepest-ascent loop of a square instance reads W (a caller-held workspace has none)
     const bool steepest = mode == Mode::Solve && !c.parallel && !c.lazy && n >= 2;
-    const bool use_w = steepest && nr == n && c.permuted;
+    const bool use_w = steepest && nr == n && c.permuted;  // (rectangular instances read A: measured no better)
     st = w ? DGS_OK : alloc_ws(n, nr, !c.dev, use_w, c.pool, s, &w);
     if (st != DGS_OK) {
         if (!c.host) release_host(h);
@@ -484,7 +484,7 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     }
     DGS_HIP(mark(DGS_PHASE_LAYOUT));
     if (!gg) DGS_HIP(launch_transpose(A, I.AT, nr, n, s));
-    if (I.W) DGS_HIP(launch_permuted(A, I.tau, n, I.W, s));
+    if (I.W) DGS_HIP(launch_permuted(A, I.tau, nr, n, I.W, s));
     DGS_HIP(launch_benefits(A, I.tau, n, nr, I.d, I.stats + 2, s));
     DGS_HIP(mark(DGS_PHASE_SCAN));
     if (c.parallel && mode == Mode::Solve)

@@ -55,8 +55,9 @@ struct Instance {
     void *glob = nullptr;        // scratch of the global greedy start
     void *scan = nullptr;        // scratch of the difference evaluation (per-block top-2)
     u64 *lists = nullptr;        // [n][kScanListLen] initial candidate lists (keys, 0 = empty)
-    int32_t *W = nullptr;        // n x n, W[r][c] = a[r][tau(c)], for the steepest-ascent loop of a square
-                                 // instance (which keeps it current), or null: that loop then reads A
+    int32_t *W = nullptr;        // n x n, W[r][c] = a[r][tau0(c)] for the start assignment tau0, read by
+                                 // the steepest-ascent loop of a square instance, or null: that loop then
+                                 // reads A
     int32_t *par = nullptr;      // [n] Parallel DGS: partner of each accepted agent, else -1
 };
 
@@ -101,8 +102,9 @@ hipError_t launch_invert_checked(const int32_t *tau, int32_t n, int32_t *sigma, 
                                  hipStream_t s);
 // AT (cols x rows) = transpose of A (rows x cols).
 hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t rows, int32_t cols, hipStream_t s);
-// W[r][c] = a[r][tau(c)] for a square n x n instance (W: n x n, device).
-hipError_t launch_permuted(const int32_t *A, const int32_t *tau, int32_t n, int32_t *W, hipStream_t s);
+// W[r][c] = a[r][tau(c)] for the rows r < rows of A (rows x n; tau: n agents; W: rows x n, device).
+hipError_t launch_permuted(const int32_t *A, const int32_t *tau, int32_t rows, int32_t n, int32_t *W,
+                           hipStream_t s);
 // d[r] = a[r][tau(r)] (0 for virtual agents r >= nr) and the objective sum.
 hipError_t launch_benefits(const int32_t *A, const int32_t *tau, int32_t n, int32_t nr, int32_t *d, int64_t *f,
                            hipStream_t s);

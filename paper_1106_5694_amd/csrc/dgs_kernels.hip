@@ -12,9 +12,9 @@
 // gain of the 2-exchange between agents r and c is
 //   g(r, c) = W[r][c] + W[c][r] - d[r] - d[c],  g(r, c) = g(c, r),
 // and column c of W is row tau(c) of AT, so the evaluation reads AT through
-// tau.  The steepest-ascent switching loop of a square instance reads rows of
-// W, so W is built for it once (k_permuted) and the loop keeps it current: a
-// switch changes two of its columns.  Agent r's candidate towards agent c is ranked
+// tau.  The steepest-ascent switching loop reads rows of W, so W is built for
+// it once from the start assignment (k_permuted); the loop reads W's column c
+// only while agent c still holds its start job.  Agent r's candidate towards agent c is ranked
 // by the packed key (gain, job tau(c)): larger gain first, lower job on ties
 // (ADE, Algorithm 2, takes the first strictly better job in index order).
 #include <hip/hip_runtime.h>
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_transpose(const int32_t *__restrict__ A
     }
 }
 
-// W[r][c] = a[r][tau(c)] for a square instance: one workgroup per row r, the
+// W[r][c] = a[r][tau(c)] for the rows r of A (n columns): one workgroup per row r, the
 // row staged through LDS in chunks of kPermChunk columns (one chunk for
 // n <= kPermChunk), then every column c takes its entry tau(c) from LDS.  With
 // VEC4 (n a multiple of 4) rows, tau and W move 16 bytes per thread and access.
@@ -190,8 +190,9 @@ hipError_t launch_transpose(const int32_t *A, int32_t *AT, int32_t rows, int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_permuted(const int32_t *A, const int32_t *tau, int32_t n, int32_t *W, hipStream_t s) {
-    if (n < 1) return hipSuccess;
+hipError_t launch_permuted(const int32_t *A, const int32_t *tau, int32_t rows, int32_t n, int32_t *W,
+                           hipStream_t s) {
+    if (rows < 1 || n < 1) return hipSuccess;
     const int shm = (int)(std::min(n, kPermChunk) * sizeof(int32_t));
     auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
     const bool vec4 = n % 4 == 0 && al16(A) && al16(tau) && al16(W);  // every row then starts 16-byte aligned
@@ -199,9 +200,9 @@ hipError_t launch_permuted(const int32_t *A, const int32_t *tau, int32_t n, int3
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, shm);
     if (e != hipSuccess) return e;
     if (vec4)
-        hipLaunchKernelGGL(k_permuted<true>, dim3((unsigned)n), dim3(kPermThreads), (unsigned)shm, s, A, tau, n, W);
+        hipLaunchKernelGGL(k_permuted<true>, dim3((unsigned)rows), dim3(kPermThreads), (unsigned)shm, s, A, tau, n, W);
     else
-        hipLaunchKernelGGL(k_permuted<false>, dim3((unsigned)n), dim3(kPermThreads), (unsigned)shm, s, A, tau, n, W);
+        hipLaunchKernelGGL(k_permuted<false>, dim3((unsigned)rows), dim3(kPermThreads), (unsigned)shm, s, A, tau, n, W);
     return hipGetLastError();
 }
 
