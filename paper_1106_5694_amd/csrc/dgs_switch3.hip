@@ -556,25 +556,20 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
         if (mine && !stall) tr2 = r == is ? js : (r == k ? j0 : tr);
         int a1 = 0, a2 = 0, w1 = 0, w2 = 0;
         const bool wcur = USEW && !moved;  // a[x][tau(r)] = W[x][r]
-        if (mine && !stall && r != is && r != k) {
-            if (USEW) {
-                a1 = P.AT[(int64_t)js * nt_ + r];  // a[r][j*]
-                a2 = P.AT[(int64_t)j0 * nt_ + r];  // a[r][j0]
-                w1 = *(wcur ? P.W + (int64_t)is * nn + r : P.A + (int64_t)is * nn + tr);  // a[i*][tau(r)]
-                w2 = *(wcur ? P.W + (int64_t)k * nn + r : P.A + (int64_t)k * nn + tr);    // a[k][tau(r)]
-            } else if (!VIRT) {
-                a1 = P.AT[(int64_t)js * nt_ + r];  // a[r][j*]
-                a2 = P.AT[(int64_t)j0 * nt_ + r];  // a[r][j0]
-                w1 = P.A[(int64_t)is * nn + tr];   // a[i*][tau(r)]
-                w2 = P.A[(int64_t)k * nn + tr];    // a[k][tau(r)]
-            } else {
-                if (real) {
-                    a1 = P.AT[(int64_t)js * nt_ + r];
-                    a2 = P.AT[(int64_t)j0 * nt_ + r];
-                }
-                w1 = P.A[(int64_t)is * nn + tr];
-                if (k < nr) w2 = P.A[(int64_t)k * nn + tr];
-            }
+        // Every lane loads under uniform conditions only: a per-lane condition costs an exec-mask
+        // branch around every load.  Lanes without an agent read column 0 and virtual agents column
+        // 0 of AT (in bounds); values a lane does not need are never used, and a virtual agent's
+        // own benefits (0) replace its AT values where they are used, after the loads' wait.
+        const int rc = mine ? r : 0, rt = real ? r : 0;
+        auto row_at_tau = [&](int x, int job) {  // a[x][job], job = tau(r) when W's column r is current
+            if constexpr (USEW) return *(wcur ? P.W + (int64_t)x * nn + rc : P.A + (int64_t)x * nn + job);
+            return P.A[(int64_t)x * nn + job];
+        };
+        if (!stall) {
+            a1 = P.AT[(int64_t)js * nt_ + rt];  // a[r][j*]
+            a2 = P.AT[(int64_t)j0 * nt_ + rt];  // a[r][j0]
+            w1 = row_at_tau(is, tr);                 // a[i*][tau(r)]
+            if (is_real(k)) w2 = row_at_tau(k, tr);  // a[k][tau(r)]
         }
         // (No branch may merge paths that hold loaded values in different registers: the
         // copy at the merge would wait for the loads.)
@@ -582,14 +577,14 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
 #pragma unroll
         for (int dd = 0; dd < kD; ++dd) {
             const int x = nx_agent[dd];
-            const bool ok = dd < nref && mine && x != is && x != k && r != x;
             ra[dd] = rb[dd] = 0;
-            if (ok) {
-                if (real) ra[dd] = P.AT[(int64_t)nx_tau[dd] * nt_ + r];  // a[r][tau(x)] (real == mine unless VIRT)
-                if (USEW)  // a[x][tau(r)] after the switch (W's column r is stale if r switches now)
-                    rb[dd] = *(wcur && r != is && r != k ? P.W + (int64_t)x * nn + r : P.A + (int64_t)x * nn + tr2);
+            if (dd < nref && x != is && x != k) {  // uniform
+                ra[dd] = P.AT[(int64_t)nx_tau[dd] * nt_ + rt];  // a[r][tau(x)]
+                // a[x][tau(r)] after the switch (W's column r is stale if r switches now)
+                if constexpr (USEW)
+                    rb[dd] = *(wcur && r != is && r != k ? P.W + (int64_t)x * nn + rc : P.A + (int64_t)x * nn + tr2);
                 else
-                    rb[dd] = P.A[(int64_t)x * nn + tr2];  // a[x][tau(r)] after the switch
+                    rb[dd] = P.A[(int64_t)x * nn + tr2];
             }
         }
         int dis = 0, dk = 0;
@@ -665,8 +660,9 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             gsum += gw;
             u64 s0 = 0, s1 = 0;
             if (mine) {
-                const int g1 = (a1 + w1) - (dr + dis);  // g(r, i*)
-                const int g2 = (a2 + w2) - (dr + dk);   // g(r, k)
+                const bool own_row = !VIRT || real;  // a virtual agent's benefits are 0
+                const int g1 = ((own_row ? a1 : 0) + w1) - (dr + dis);  // g(r, i*)
+                const int g2 = ((own_row ? a2 : 0) + w2) - (dr + dk);   // g(r, k)
                 const bool switched = r == is || r == k;
                 list_drop_jobs(L, js, j0);
                 list_insert(L, B, le_key(g1, js, is));
@@ -699,7 +695,8 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
             const int x = nx_agent[dd];
             if (dd < nref && x != is && x != k) {  // uniform
                 u64 v = 0;
-                if (mine && r != x) v = le_key((ra[dd] + rb[dd]) - (dr + nx_d[dd]), tr, t);  // g(r, x)
+                if (mine && r != x)  // g(r, x) (a virtual agent's benefit a[r][tau(x)] is 0)
+                    v = le_key((((!VIRT || real) ? ra[dd] : 0) + rb[dd]) - (dr + nx_d[dd]), tr, t);
                 if (mine && r == x) inflight = true;
                 vals[2 + jn][t] = v;
                 if (t == 0) tgn[jn] = make_int2(x, nx_tau[dd]);
