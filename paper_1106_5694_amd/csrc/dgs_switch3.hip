@@ -488,7 +488,15 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                     for (int i = 0; i < kD; ++i) rank += i < m && pend[i] > me;
                     choose(rank, me, pend_at[lane]);
                 }
-            } else {  // the kD largest by repeated maxima
+            } else {  // the kD largest by repeated maxima; the chosen agents' lookups after the loop
+                      // (inside it, each was a dependent LDS round trip)
+                int rk[kPer];
+                u64 k0[kPer];
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    rk[i] = kD;
+                    k0[i] = kk[i];
+                }
                 for (int rank = 0; rank < kD; ++rank) {
                     u64 mx = 0;
 #pragma unroll
@@ -496,12 +504,14 @@ __global__ __launch_bounds__(kT) void k_switch_v3(V3Params P) {
                     const u64 top = wave_max(mx);
 #pragma unroll
                     for (int i = 0; i < kPer; ++i) {
-                        if (kk[i] == top) {  // one lane, one slot: keys are unique
-                            choose(rank, top, lane + 64 * i);
-                            kk[i] = 0;
-                        }
+                        const bool hit = kk[i] == top;  // one lane, one slot: keys are unique
+                        rk[i] = hit ? rank : rk[i];
+                        kk[i] = hit ? 0 : kk[i];
                     }
                 }
+#pragma unroll
+                for (int i = 0; i < kPer; ++i)
+                    if (rk[i] < kD) choose(rk[i], k0[i], lane + 64 * i);
             }
         }
         __syncthreads();
