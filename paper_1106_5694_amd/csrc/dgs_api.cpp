@@ -424,7 +424,8 @@ dgs_status run_instance(const Call &c, Mode mode, int32_t *assign_out, int64_t *
     Workspace *w = c.ws;
     // the steepest-ascent loop of a square instance reads W (a caller-held workspace has none)
     const bool steepest = mode == Mode::Solve && !c.parallel && !c.lazy && n >= 2;
-    const bool use_w = steepest && nr == n && c.permuted;  // (rectangular instances read A: measured no better)
+    // (rectangular instances read A: measured no better; a call without switches needs no W)
+    const bool use_w = steepest && nr == n && c.permuted && c.max_switches != 0;
     st = w ? DGS_OK : alloc_ws(n, nr, !c.dev, use_w, c.pool, s, &w);
     if (st != DGS_OK) {
         if (!c.host) release_host(h);
